@@ -1,0 +1,22 @@
+"""Seeded synthetic workloads (velocity, reflectivity, acquisition geometry,
+noise and test vectors) shared by the oracle tests, the GPU tests and the
+benchmark.
+
+This package describes inputs only. It contains none of the method's
+arithmetic (no wavelet, stencil, sponge, propagation or solver); both the GPU
+library and the CPU oracle implement those themselves.
+"""
+from .configs import (  # noqa: F401
+    CONFIG_NAMES,
+    Workload,
+    Shot,
+    workload,
+    config0,
+    config1,
+    config3,
+    noise_like,
+    tiny2d,
+    tiny3d,
+    rng,
+    gaussian,
+)

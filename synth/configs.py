@@ -1,0 +1,290 @@
+"""Workload descriptions with the shapes, sizes and value distributions of the
+method's use cases.
+
+The paper's own example (Examples section) migrates the Marmousi data set
+(240 shots, 25 m apart, 20 Hz Ricker, windows of 5 shots sliding by 3). That
+model and data are not available here, so every workload below is synthetic
+and seeded: a layered, faulted 2-D model whose velocity rises with depth
+stands in for Marmousi.
+
+Naming: ``Q`` is the number of shots in a window (the paper's window length)
+and ``S`` is the number of shots added and dropped per slide (the paper's
+rank of update and downdate).
+
+Seeds: ``numpy.random.default_rng(1000 * c + k)`` with c the workload index
+and k = 0 reflectivity, 1 noise, 2 test vectors / finite-difference
+directions, 3 faults and drift.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+CONFIG_NAMES = {
+    0: "layers2d-64x64",
+    1: "faulted2d-512x1024",
+    2: "faulted2d-512x1024-autograd",
+    3: "layered3d-256x320x320",
+    4: "faulted2d-512x1024-stream",
+}
+
+
+def rng(config_index: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(1000 * config_index + stream)
+
+
+def gaussian(shape, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+@dataclass
+class Shot:
+    id: int
+    src: tuple  # (z, y, x) on the model grid (y = 0 in 2-D)
+    rec: np.ndarray  # int32 [nrec, 3] (z, y, x) on the model grid
+    nt: int
+    f0: float
+
+    @property
+    def nrec(self) -> int:
+        return int(self.rec.shape[0])
+
+
+@dataclass
+class Workload:
+    name: str
+    index: int
+    ndim: int
+    nz: int
+    ny: int
+    nx: int
+    nb: int
+    h: float
+    dt: float
+    nt: int
+    f0: float
+    vel: np.ndarray  # float64 [nz, ny, nx], m/s
+    m_true: np.ndarray  # float64 [nz, ny, nx]
+    shots: List[Shot]
+    Q: int
+    S: int
+    niter: int
+    lam_rel: float
+    noise_rel: float = 0.01
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def model_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def npoints_model(self) -> int:
+        return self.nz * self.ny * self.nx
+
+    @property
+    def npoints_padded(self) -> int:
+        py = self.ny + 2 * self.nb if self.ndim == 3 else 1
+        return (self.nz + 2 * self.nb) * py * (self.nx + 2 * self.nb)
+
+    def windows(self) -> List[List[int]]:
+        """Shot indices of each window: window w holds [wS, wS + Q)."""
+        out = []
+        n = len(self.shots)
+        if n <= self.Q:
+            return [list(range(n))]
+        w = 0
+        while w * self.S + self.Q <= n:
+            out.append(list(range(w * self.S, w * self.S + self.Q)))
+            w += 1
+        last = out[-1][-1]
+        if last < n - 1:  # final shorter slide
+            out.append(list(range(n - self.Q, n)))
+        return out
+
+
+def _row_receivers(z: int, xs, y: int = 0) -> np.ndarray:
+    xs = np.asarray(list(xs), dtype=np.int32)
+    out = np.zeros((xs.size, 3), dtype=np.int32)
+    out[:, 0] = z
+    out[:, 1] = y
+    out[:, 2] = xs
+    return out
+
+
+def config0() -> Workload:
+    """2-D, 64 x 64, h = 10 m, constant 2000 m/s, three flat reflectors."""
+    nz = nx = 64
+    r = rng(0, 0)
+    amps = r.uniform(-0.1, 0.1, size=3)
+    m = np.zeros((nz, 1, nx))
+    for a, z in zip(amps, (20, 35, 50)):
+        m[z, 0, :] = a
+    vel = np.full((nz, 1, nx), 2000.0)
+    rec = _row_receivers(2, range(64))
+    shots = [Shot(i, (2, 0, x), rec.copy(), 500, 15.0)
+             for i, x in enumerate((8, 24, 40, 56))]
+    return Workload(CONFIG_NAMES[0], 0, 2, nz, 1, nx, 20, 10.0, 1e-3, 500,
+                    15.0, vel, m, shots, Q=2, S=1, niter=10, lam_rel=0.01)
+
+
+def faulted_reflectivity(nz: int, nx: int, r_layers, r_faults,
+                         nlayers: int = 40, nfaults: int = 10) -> np.ndarray:
+    """Vertical derivative of a random layered model cut by dipping faults,
+    scaled to max |m| = 0.1."""
+    xc = (nx - 1) / 2.0
+    depths = np.sort(r_layers.uniform(16, nz - 12, size=nlayers))
+    dips = r_layers.uniform(-0.05, 0.05, size=nlayers)
+    values = r_layers.uniform(-1.0, 1.0, size=nlayers + 1)
+    faults = []
+    for _ in range(nfaults):
+        x0 = r_faults.uniform(100, nx - 100) if nx > 240 else r_faults.uniform(
+            0.2 * nx, 0.8 * nx)
+        ang = np.deg2rad(r_faults.uniform(60.0, 80.0))
+        throw = r_faults.uniform(4, 16)
+        side = 1.0 if r_faults.uniform() < 0.5 else -1.0
+        faults.append((x0, side / np.tan(ang), throw))
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    zeff = np.broadcast_to(z, (nz, nx)).copy()
+    for x0, slope, throw in faults:
+        hanging = x > x0 + slope * z  # right of the fault plane
+        zeff = np.where(hanging, zeff - throw, zeff)
+    # layer index below each interface
+    b = np.full((nz, nx), values[0])
+    for i in range(nlayers):
+        iface = depths[i] + dips[i] * (x - xc)
+        b = np.where(zeff >= iface, values[i + 1], b)
+    m = np.zeros((nz, nx))
+    m[:-1] = b[1:] - b[:-1]
+    mx = np.abs(m).max()
+    if mx > 0:
+        m *= 0.1 / mx
+    return m
+
+
+def config1(nz: int = 512, nx: int = 1024, nshots: int = 64,
+            nt: int = 3000) -> Workload:
+    """2-D, 512 x 1024, h = 5 m, v(z) 1500 -> 4000 m/s with a -300 m/s
+    Gaussian anomaly (sigma 200 m), faulted layered reflectivity, 64 shots
+    80 m apart, 1024 receivers, nt = 3000, dt = 0.5 ms, 20 Hz."""
+    h = 5.0
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    zc, xc = 1280.0 * nz / 512.0, 2560.0 * nx / 1024.0
+    sig = 200.0
+    vel = 1500.0 + 2500.0 * z / (nz - 1) - 300.0 * np.exp(
+        -(((z * h - zc) ** 2 + (x * h - xc) ** 2) / (2 * sig * sig)))
+    m = faulted_reflectivity(nz, nx, rng(1, 0), rng(1, 3))
+    rec = _row_receivers(2, range(nx))
+    spacing = 16
+    shots = [Shot(i, (2, 0, 8 + spacing * i), rec.copy(), nt, 20.0)
+             for i in range(nshots) if 8 + spacing * i < nx]
+    return Workload(CONFIG_NAMES[1], 1, 2, nz, 1, nx, 40, h, 0.5e-3, nt, 20.0,
+                    vel[:, None, :].copy(), m[:, None, :].copy(), shots, Q=8,
+                    S=4, niter=20, lam_rel=1e-3)
+
+
+def config3(nz: int = 256, ny: int = 320, nx: int = 320, nt: int = 2000,
+            nrec_side: int = 128) -> Workload:
+    """3-D, 256 x 320 x 320, h = 10 m, v(z) 1500 -> 3500 m/s, random layered
+    reflectivity, 32 shots on an 8 x 4 grid, 128 x 128 receivers,
+    nt = 2000, dt = 1 ms, 12 Hz."""
+    h = 10.0
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    vel = np.broadcast_to(1500.0 + 2000.0 * z / (nz - 1), (nz, ny, nx)).copy()
+    r = rng(3, 0)
+    nl = 30
+    depths = r.uniform(10, nz - 6, size=nl)
+    dx = r.uniform(-0.03, 0.03, size=nl)
+    dy = r.uniform(-0.03, 0.03, size=nl)
+    amps = r.uniform(-0.1, 0.1, size=nl)
+    m = np.zeros((nz, ny, nx))
+    yy, xx = np.meshgrid(np.arange(ny) - (ny - 1) / 2.0,
+                         np.arange(nx) - (nx - 1) / 2.0, indexing="ij")
+    for i in range(nl):
+        zi = np.rint(depths[i] + dx[i] * xx + dy[i] * yy).astype(int)
+        ok = (zi >= 0) & (zi < nz)
+        iy, ix = np.nonzero(ok)
+        m[zi[ok], iy, ix] += amps[i]
+    step = max(1, min((nx - 4) // nrec_side, (ny - 4) // nrec_side))
+    off_x = (nx - step * (nrec_side - 1)) // 2
+    off_y = (ny - step * (nrec_side - 1)) // 2
+    ry, rx = np.meshgrid(off_y + step * np.arange(nrec_side),
+                         off_x + step * np.arange(nrec_side), indexing="ij")
+    rec = np.stack([np.full(rx.size, 2), ry.ravel(), rx.ravel()],
+                   axis=1).astype(np.int32)
+    sxs = [int(round((i + 0.5) * nx / 8)) for i in range(8)]
+    sys_ = [int(round((j + 0.5) * ny / 4)) for j in range(4)]
+    shots = []
+    for j, sy in enumerate(sys_):
+        for i, sx in enumerate(sxs):
+            shots.append(Shot(len(shots), (2, sy, sx), rec.copy(), nt, 12.0))
+    return Workload(CONFIG_NAMES[3], 3, 3, nz, ny, nx, 20, h, 1e-3, nt, 12.0,
+                    vel, m, shots, Q=8, S=4, niter=20, lam_rel=1e-3)
+
+
+def tiny2d(nz: int = 12, nx: int = 12, nb: int = 6, nt: int = 120,
+           nshots: int = 2, nrec: int = 12, seed: int = 7,
+           velocity: str = "gradient") -> Workload:
+    """Small 2-D problem for dense-matrix checks and parity at a few tiles."""
+    r = np.random.default_rng(seed)
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    if velocity == "constant":
+        vel = np.full((nz, nx), 2000.0)
+    else:
+        vel = 1800.0 + 600.0 * z / max(nz - 1, 1) + 100.0 * r.uniform(
+            -1, 1, size=(nz, nx))
+    m = r.uniform(-0.1, 0.1, size=(nz, nx))
+    xs = np.linspace(1, nx - 2, nrec).round().astype(int)
+    rec = _row_receivers(min(2, nz - 1), xs)
+    sx = np.linspace(2, nx - 3, nshots).round().astype(int)
+    shots = [Shot(i, (min(2, nz - 1), 0, int(x)), rec.copy(), nt, 25.0)
+             for i, x in enumerate(sx)]
+    return Workload("tiny2d", -1, 2, nz, 1, nx, nb, 10.0, 1e-3, nt, 25.0,
+                    vel[:, None, :].copy(), m[:, None, :].copy(), shots,
+                    Q=nshots, S=1, niter=10, lam_rel=0.01)
+
+
+def tiny3d(nz: int = 8, ny: int = 8, nx: int = 8, nb: int = 4, nt: int = 80,
+           nshots: int = 2, seed: int = 11) -> Workload:
+    r = np.random.default_rng(seed)
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    vel = np.broadcast_to(1800.0 + 500.0 * z / (nz - 1),
+                          (nz, ny, nx)) + 80.0 * r.uniform(-1, 1,
+                                                           (nz, ny, nx))
+    m = r.uniform(-0.1, 0.1, size=(nz, ny, nx))
+    ry, rx = np.meshgrid(np.arange(1, ny - 1, 2), np.arange(1, nx - 1, 2),
+                         indexing="ij")
+    rec = np.stack([np.full(rx.size, 1), ry.ravel(), rx.ravel()],
+                   axis=1).astype(np.int32)
+    shots = [Shot(i, (1, 2 + 3 * i % (ny - 2), 2 + 2 * i % (nx - 2)),
+                  rec.copy(), nt, 30.0) for i in range(nshots)]
+    return Workload("tiny3d", -1, 3, nz, ny, nx, nb, 10.0, 1e-3, nt, 30.0,
+                    np.ascontiguousarray(vel), m, shots, Q=nshots, S=1,
+                    niter=10, lam_rel=0.01)
+
+
+def workload(index: int, **kw) -> Workload:
+    if index == 0:
+        return config0()
+    if index in (1, 2):
+        w = config1(**kw)
+        if index == 2:
+            w.name, w.index = CONFIG_NAMES[2], 2
+        return w
+    if index == 3:
+        return config3(**kw)
+    raise ValueError(f"no workload {index}")
+
+
+def noise_like(shape, config_index: int) -> np.ndarray:
+    return rng(config_index, 1).standard_normal(shape)
+
+
+def unit_random_like(shape, seed: int, norm: Optional[float] = None):
+    v = gaussian(shape, seed)
+    if norm is not None:
+        v *= norm / np.linalg.norm(v)
+    return v

@@ -1,0 +1,173 @@
+"""Pins of the oracle's damped least-squares solver and block-row recursion
+against dense linear algebra (eqs. 3-11 of the paper) on tiny problems."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def dense_problem(orc):
+    w = synth.tiny2d(nz=8, nx=9, nb=4, nt=150, nrec=6, nshots=3, seed=3)
+    prob = orc.Problem.from_workload(w)
+    M = int(np.prod(prob.grid.model_shape))
+    blocks = []
+    for i in range(3):
+        cols = []
+        for j in range(M):
+            e = np.zeros(M)
+            e[j] = 1.0
+            cols.append(prob.born_shot(i, e).ravel())
+        blocks.append(np.stack(cols, 1))
+    noise = [synth.gaussian(prob.data_shape(i), 100 + i) for i in range(3)]
+    data = orc.synthesize_data(prob, w.m_true, 0.01, noise)
+    A = np.concatenate(blocks, 0)
+    lam = 0.01 * np.linalg.norm(A, 2) ** 2
+    return dict(w=w, prob=prob, blocks=blocks, data=data, lam=lam, M=M)
+
+
+def _textbook_cg(H, b, x0, niter):
+    """Hestenes-Stiefel CG on H x = b."""
+    x = x0.copy()
+    r = b - H @ x
+    p = r.copy()
+    rr = r @ r
+    xs = [x.copy()]
+    for _ in range(niter):
+        Hp = H @ p
+        a = rr / (p @ Hp)
+        x = x + a * p
+        r = r - a * Hp
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        xs.append(x.copy())
+    return xs
+
+
+def _normal(dp, idx):
+    A = np.concatenate([dp["blocks"][i] for i in idx], 0)
+    d = np.concatenate([dp["data"][i].ravel() for i in idx])
+    H = A.T @ A + dp["lam"] * np.eye(dp["M"])
+    return A, d, H, A.T @ d
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_cgls_iterates_equal_textbook_cg_on_normal_equations(orc, dense_problem,
+                                                              warm):
+    dp = dense_problem
+    idx = [0, 1]
+    A, d, H, b = _normal(dp, idx)
+    x0 = synth.gaussian(dp["M"], 5) * 0.05 if warm else np.zeros(dp["M"])
+    ref = _textbook_cg(H, b, x0, 8)
+    res = orc.cgls(dp["prob"], idx, [dp["data"][i] for i in idx], dp["lam"], 8,
+                   m0=x0.reshape(dp["prob"].grid.model_shape),
+                   keep_iterates=True)
+    assert res.iters == 8
+    for k, (xr, xo) in enumerate(zip(ref, res.iterates)):
+        rel = np.linalg.norm(xo.ravel() - xr) / max(np.linalg.norm(xr), 1e-300)
+        assert rel < 1e-10, (k, rel)
+
+
+def test_cgls_converges_to_closed_form(orc, dense_problem):
+    """Eq. 4: m = (A^T A + lam I)^-1 A^T d."""
+    dp = dense_problem
+    idx = [0, 1, 2]
+    A, d, H, b = _normal(dp, idx)
+    exact = np.linalg.solve(H, b)
+    res = orc.cgls(dp["prob"], idx, [dp["data"][i] for i in idx], dp["lam"],
+                   120)
+    assert np.linalg.norm(res.m.ravel() - exact) <= 1e-9 * np.linalg.norm(
+        exact)
+    # residual norms of the normal equations shrink overall
+    assert res.s_norms[-1] < 1e-9 * res.s_norms[0]
+
+
+def test_one_window_over_all_shots_is_batch_least_squares(orc, dense_problem):
+    dp = dense_problem
+    A, d, H, b = _normal(dp, [0, 1, 2])
+    ch = orc.chain(dp["prob"], dp["data"], [[0, 1, 2]], dp["lam"], 120)
+    assert np.linalg.norm(ch.m.ravel() - np.linalg.solve(H, b)) <= 1e-9 * \
+        np.linalg.norm(ch.m)
+
+
+def test_warm_start_does_not_change_the_window_solution(orc, dense_problem):
+    """Eq. 11: the warm-started correction reaches the window's own
+    least-squares solution whatever the starting image."""
+    dp = dense_problem
+    idx = [1, 2]
+    d = [dp["data"][i] for i in idx]
+    a = orc.cgls(dp["prob"], idx, d, dp["lam"], 120)
+    m0 = synth.gaussian(dp["prob"].grid.model_shape, 9)
+    b = orc.cgls(dp["prob"], idx, d, dp["lam"], 120, m0=m0)
+    assert np.linalg.norm(a.m - b.m) <= 1e-9 * np.linalg.norm(a.m)
+
+
+def test_rls_update_and_downdate_identities(orc, dense_problem):
+    """Eqs. 5-9 with the damping folded into P0: the gain-form update equals
+    the batch solution of both blocks; the mirror downdate recovers the
+    solution of the remaining block; the chain of converged windows equals
+    that recursion."""
+    dp = dense_problem
+    A0, A1, A2 = dp["blocks"]
+    d0, d1, d2 = [x.ravel() for x in dp["data"]]
+    lam, I = dp["lam"], np.eye(dp["M"])
+    P0inv = A0.T @ A0 + lam * I
+    m0 = np.linalg.solve(P0inv, A0.T @ d0)
+    P1inv = P0inv + A1.T @ A1  # eq. 8
+    m1 = m0 + np.linalg.solve(P1inv, A1.T @ (d1 - A1 @ m0))  # eq. 9
+    batch01 = np.linalg.solve(A0.T @ A0 + A1.T @ A1 + lam * I,
+                              A0.T @ d0 + A1.T @ d1)  # eq. 7
+    assert np.linalg.norm(m1 - batch01) <= 1e-10 * np.linalg.norm(batch01)
+    # downdate block 0, then update block 2: the window slides by one shot
+    P2inv = P1inv - A0.T @ A0
+    m2 = m1 - np.linalg.solve(P2inv, A0.T @ (d0 - A0 @ m1))
+    only1 = np.linalg.solve(A1.T @ A1 + lam * I, A1.T @ d1)
+    assert np.linalg.norm(m2 - only1) <= 1e-9 * np.linalg.norm(only1)
+    P3inv = P2inv + A2.T @ A2
+    m3 = m2 + np.linalg.solve(P3inv, A2.T @ (d2 - A2 @ m2))
+    ch = orc.chain(dp["prob"], dp["data"], [[0, 1], [1, 2]], lam, 150)
+    for img, ref in ((ch.images[0], m1), (ch.images[1], m3)):
+        assert np.linalg.norm(img.ravel() - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_truncated_chain_replays_dense_cg(orc, dense_problem):
+    """The truncated, warm-started chain (the method's actual output) equals
+    the same chain run with textbook CG on the dense normal equations."""
+    dp = dense_problem
+    wins = [[0, 1], [1, 2]]
+    ch = orc.chain(dp["prob"], dp["data"], wins, dp["lam"], 6)
+    x = np.zeros(dp["M"])
+    for w, img in zip(wins, ch.images):
+        A, d, H, b = _normal(dp, w)
+        x = _textbook_cg(H, b, x, 6)[-1]
+        assert np.linalg.norm(img.ravel() - x) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_power_norm_matches_spectral_norm(orc, dense_problem):
+    dp = dense_problem
+    A = np.concatenate(dp["blocks"][:2], 0)
+    est = orc.power_norm(dp["prob"], [0, 1], 60, seed=4)
+    assert abs(est - np.linalg.norm(A, 2) ** 2) <= 1e-6 * est
+
+
+def test_paper_window_schedule():
+    """The paper's example: windows of Q = 5 shots, K = 3 dropped and added
+    per step, steps t = Q, Q+K, ... over 240 shots."""
+    with open(os.path.join(HERE, "golden", "paper_example.json")) as f:
+        g = json.load(f)
+    Q, K, N = g["window_shots_Q"], g["update_downdate_rank_K"], g["shots"]
+    w = synth.tiny2d(nshots=N, nz=4, nx=N + 4, nb=1)
+    w.Q, w.S = Q, K
+    wins = w.windows()
+    ends = [win[-1] + 1 for win in wins]
+    assert ends[:-1] == list(range(Q, N + 1, K))[:len(ends) - 1]
+    assert all(len(win) == Q for win in wins)
+    for a, b in zip(wins, wins[1:-1]):
+        assert len(set(a) - set(b)) == K and len(set(b) - set(a)) == K
+    assert wins[-1][-1] == N - 1
