@@ -1,0 +1,302 @@
+"""Benchmark: block-row recursive least-squares migration, one MI355X.
+
+Workload (the paper's method on the faulted 2-D model): 512 x 1024 grid,
+h = 5 m, 40-cell sponge (592 x 1104 padded), 64 shots 80 m apart with 1024
+receivers each, nt = 3000 at dt = 0.5 ms, 20 Hz Ricker; windows of Q = 8
+shots sliding by S = 4; 20 CG iterations per window; lambda = 1e-3 relative
+to ||A_w^T A_w|| of the first window.
+
+One step = one window of the chain: downdate the S oldest shots, update the
+S new ones (data already resident in device memory), build their background
+wavefields, run the warm-started CG solve, copy the image out.
+
+value = Born + adjoint grid-point updates per second over the timed steps
+(every propagated Born-field and adjoint-field point per time step and shot,
+background propagation not counted, time of everything in the step counted).
+
+Prints one JSON line. Also reports the roofline of the dominant kernel
+(event-timed in a separate pass) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-sample-nt", type=int, default=800)
+    ap.add_argument("--only-steps", action="store_true",
+                    help="time the steps only (for profiler runs)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec):
+    """Bytes one batched time-step launch must move at minimum (float32):
+    per shot and padded point u read, v read, v write, u write (16 B) and
+    the Born-source cache on the model region (4 B); per block group the
+    medium W' (4 B/point) and the model vector (Born: 4 B) or the float64
+    image accumulator read and written (adjoint: 16 B) on the model region;
+    per shot the receiver samples (4 B each)."""
+    per_shot = 16 * npad + 4 * nint + 4 * nrec
+    if kind == "born":
+        shared = 4 * npad + 4 * nint
+    else:
+        shared = 4 * npad + 16 * nint
+    return Q * per_shot + ngroups * shared
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "--gpus must be 1 (multi-GPU sharding by shot is "
+                          "a design note, not implemented)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1801_00819_amd as P
+    import synth
+
+    torch.cuda.set_device(0)
+    w = synth.config1()
+    Q, S = w.Q, w.S
+    nshots = len(w.shots)
+    nrec = w.shots[0].nrec
+    nt = w.nt
+    pz, px = w.nz + 2 * w.nb, w.nx + 2 * w.nb
+    npad, nint = pz * px, w.nz * w.nx
+    vel = w.vel.astype(np.float32)
+    m_true = torch.from_numpy(w.m_true.astype(np.float32)).cuda()
+
+    # ---- setup (untimed): data d = A m_true + 1% noise, lambda ----------
+    t_setup = time.perf_counter()
+    ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt, nrec, Q, w.h, w.dt, 0.0,
+                      vel, device=True)
+    data = torch.empty((nshots, nt, nrec), dtype=torch.float32, device="cuda")
+    for b in range(0, nshots, Q):
+        ids = list(range(b, min(b + Q, nshots)))
+        for i in ids:
+            s = w.shots[i]
+            ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+        d = ctx.apply_born(m_true)
+        data[ids[0]:ids[-1] + 1] = d.view(len(ids), nt, nrec)
+        for i in ids:
+            ctx.downdate(i)
+    rms = float(torch.sqrt(torch.mean(data.double() ** 2)))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1001)
+    data += 0.01 * rms * torch.randn(data.shape, generator=gen,
+                                     device="cuda")
+    win0 = w.windows()[0]
+    for i in win0:
+        s = w.shots[i]
+        ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+    x = torch.from_numpy(synth.gaussian(w.model_shape, 2002).astype(
+        np.float32)).cuda()
+    x /= torch.linalg.vector_norm(x)
+    norm = 0.0
+    for _ in range(8):
+        y = ctx.apply_adjoint(ctx.apply_born(x))
+        norm = float(torch.linalg.vector_norm(y.double()))
+        x = y / norm
+    lam = w.lam_rel * norm
+    ctx.close()
+    torch.cuda.synchronize()
+    log(f"setup: data + lambda {time.perf_counter() - t_setup:.1f}s "
+        f"(||A^T A|| ~ {norm:.4e}, lambda = {lam:.4e})")
+
+    # ---- the chain ---------------------------------------------------------
+    ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt, nrec, Q, w.h, w.dt, lam,
+                      vel, device=True)
+    ctx.set_exec(P.BRLS_EXEC_GRAPH)
+    windows = w.windows()
+    held = []
+    image = torch.empty(w.model_shape, dtype=torch.float32, device="cuda")
+
+    def step(k):
+        win = windows[k % len(windows)]
+        for i in list(held):  # rank-S downdate
+            if i not in win:
+                ctx.downdate(i)
+                held.remove(i)
+        for i in win:  # rank-S update
+            if i not in held:
+                s = w.shots[i]
+                ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+                held.append(i)
+        st = ctx.solve_window(args.iters)
+        ctx.image(image)
+        return st
+
+    if not args.no_autotune and not args.only_steps:
+        for i in win0:
+            s = w.shots[i]
+            ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+            held.append(i)
+        t = time.perf_counter()
+        best = ctx.autotune()
+        log(f"autotune: variant {ctx.get_tile()} "
+            f"({P.tile_variants()[best]}) in {time.perf_counter() - t:.1f}s")
+
+    nwin = args.warmup + args.steps
+    if nwin > len(windows):
+        log(f"note: {nwin} steps > {len(windows)} windows; the chain wraps")
+    for k in range(args.warmup):
+        st = step(k)
+        log(f"warmup step {k}: {st}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.warmup, nwin):
+        stats.append(step(k))
+        log(f"step {k}: iters={stats[-1]['iters']} "
+            f"s={stats[-1]['seconds']:.3f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ops = sum(2 * (1 + s["iters"]) for s in stats)
+    updates = ops * Q * npad * (nt - 1)
+    value = updates / elapsed / 1e9
+    ms_per_step = elapsed / args.steps * 1e3
+
+    out = {
+        "metric": "Born+adjoint Gpt-updates/s",
+        "value": round(value, 3),
+        "unit": "Gpt-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "faulted2d-512x1024: 64 shots x 1024 receivers, "
+                        "nt=3000, window 8 shots sliding by 4, 20 CG iters",
+            "padded_grid": [pz, px],
+            "window_shots": Q,
+            "slide": S,
+            "cg_iters": args.iters,
+            "exec": "graph",
+            "tile_variant": list(ctx.get_tile()),
+        },
+        "s_per_window": round(elapsed / args.steps, 4),
+        "cg_scalars": "f64",
+    }
+    if args.only_steps:
+        print(json.dumps(out), flush=True)
+        ctx.close()
+        return
+
+    # ---- roofline of the dominant kernel (event-timed launches) ----------
+    ctx.set_exec(P.BRLS_EXEC_BATCHED)
+    ctx.kernel_timing(True)
+    dwin = ctx.apply_born(m_true)
+    ctx.apply_adjoint(dwin)
+    ks = ctx.kernel_stats()
+    ctx.kernel_timing(False)
+    var, pb = ctx.get_tile()
+    ngroups = (Q + pb - 1) // pb
+    roof = {}
+    for kind, name in (("born", "born_step"), ("adjoint", "adjoint_step")):
+        n, ms = ks[name]
+        avg_s = ms / n / 1e3
+        byt = algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec)
+        roof[kind] = dict(avg_us=avg_s * 1e6, bytes=byt,
+                          gbs=byt / avg_s / 1e9)
+    dom = max(roof, key=lambda k: roof[k]["avg_us"])
+    r = roof[dom]
+    out["roofline"] = {
+        "bound": "hbm",
+        "kernel": f"{dom}_step (k_step2d, {P.tile_variants()[var]}, "
+                  f"{pb} shots/block)",
+        "achieved": round(r["gbs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_us": round(r["avg_us"], 2),
+        "algorithmic_bytes_per_launch": r["bytes"],
+        "other": {k: {"avg_launch_us": round(v["avg_us"], 2),
+                      "achieved_GBs": round(v["gbs"], 1)}
+                  for k, v in roof.items() if k != dom},
+    }
+    log(f"roofline: {roof}")
+
+    # ---- plain per-shot launches, same operator pair ------------------
+    if not args.no_plain:
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        res = {}
+        for mode, name in ((P.BRLS_EXEC_PLAIN, "plain"),
+                           (P.BRLS_EXEC_GRAPH, "graph")):
+            ctx.set_exec(mode)
+            ctx.apply_born(m_true)  # graph capture outside the timing
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.apply_born(m_true)
+            ctx.apply_adjoint(dwin)
+            torch.cuda.synchronize()
+            res[name] = time.perf_counter() - t
+        del ev0, ev1
+        pair_updates = 2 * Q * npad * (nt - 1)
+        out["operator_pair"] = {
+            k: {"seconds": round(v, 4),
+                "Gpt_updates_per_s": round(pair_updates / v / 1e9, 2)}
+            for k, v in res.items()}
+        log(f"operator pair: {out['operator_pair']}")
+    ctx.close()
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample -------------
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = args.cpu_sample_nt
+        s0 = w.shots[0]
+        shot = synth.Shot(0, s0.src, s0.rec, ns, s0.f0)
+        grid = oracle.Grid(2, w.nz, 1, w.nx, w.nb, w.h, w.dt)
+        prob = oracle.Problem(grid, vel.astype(np.float64), [shot])
+        m64 = w.m_true.astype(np.float64)
+        t = time.perf_counter()
+        d = prob.born_shot(0, m64)
+        prob.adjoint_shot(0, d)
+        tc = time.perf_counter() - t
+        cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+        out["cpu_baseline"] = {
+            "value": round(2 * npad * (ns - 1) / tc / 1e9, 4),
+            "unit": "Gpt-updates/s",
+            "cores": cores,
+            "kind": "oracle",
+            "sample": f"1 shot, nt={ns} (of 3000), one Born + one adjoint "
+                      f"application, FP64, {tc:.1f}s",
+        }
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * brrlsm — block-row recursive least-squares migration on MI355X (gfx950).
+ *
+ * C ABI of the library. It follows the method of Kazemi & Sacchi, "Block row
+ * recursive least squares migration" (CSEG 2015, arXiv 1801.00819):
+ *
+ *   - eq. 1 (d = A m + n) and eq. 2 (migration = A^T d): A is wave-equation
+ *     Born modelling on a regular grid and A^T its exact discrete adjoint;
+ *   - eq. 3 / eq. 10: each window of shots solves
+ *       min ||A_w m - d_w||^2 + lambda ||m||^2
+ *     by conjugate gradients on the least-squares form (normal equations
+ *     eq. 4, never formed);
+ *   - eq. 10-11 and Fig. 1: the window slides by adding shots (update) and
+ *     removing the oldest ones (downdate); each solve starts from the image of
+ *     the previous window (warm start).
+ *
+ * The operator is the two-way acoustic Born operator: 8th-order (radius 4)
+ * central differences in space, second order in time, absorbing sponge of nb
+ * cells on every face, Ricker source (delay 1.5/f0), sources and receivers on
+ * grid points, m = relative perturbation of squared slowness.
+ *
+ * Conventions
+ *   - Model-space arrays (velocity, image, m): [nz][ny][nx] row-major, x
+ *     fastest, ny = 1 in 2-D. float32 unless stated.
+ *   - Shot data: [nt][nrec] per shot, float32. Window data are the shots'
+ *     arrays concatenated in window order (the order shots were added).
+ *   - Every function returns BRLS_OK (0) or a negative BRLS_E* code; the
+ *     message of the last error is available from brls_last_error. Nothing
+ *     throws across the ABI.
+ *   - Pointers to shot data, images and window data are host pointers unless
+ *     the context was opened with BRLS_DEVICE_PTRS, in which case they are
+ *     device pointers valid on the context's stream. Geometry and velocity
+ *     are always host pointers. The library copies every input at call time;
+ *     the caller keeps ownership of all buffers it passes.
+ *   - A context is bound to the device current at brls_open and to the
+ *     stream given there; it is not thread-safe. All work is ordered on that
+ *     stream. Functions that return host results synchronise the stream.
+ */
+#ifndef BRRLSM_H
+#define BRRLSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BRLS_OK 0
+#define BRLS_EINVAL (-1)     /* bad argument, shape, position or CFL */
+#define BRLS_ENOMEM (-2)     /* device allocation failed */
+#define BRLS_EFULL (-3)      /* window already holds q_max shots */
+#define BRLS_ENOSHOT (-4)    /* no shot with that id in the window */
+#define BRLS_EBREAKDOWN (-5) /* CG breakdown: <p, (A^T A + lambda I) p> <= 0 */
+#define BRLS_ENONFINITE (-6) /* NaN or Inf in inputs or CG scalars */
+#define BRLS_EDEVICE (-7)    /* HIP runtime error or library not built for gfx950 */
+#define BRLS_EDUP (-8)       /* a shot with that id is already in the window */
+
+/* brls_grid.flags */
+#define BRLS_DEVICE_PTRS 1u
+
+/* execution modes (brls_set_exec) */
+#define BRLS_EXEC_PLAIN 0   /* one kernel launch per shot and per time step */
+#define BRLS_EXEC_BATCHED 1 /* one launch per time step for all window shots */
+#define BRLS_EXEC_GRAPH 2   /* batched; the time loop is replayed as a hipGraph */
+
+typedef struct brls_ctx brls_ctx;
+
+typedef struct {
+  int32_t ndim;       /* 2 (implemented); 3 is rejected with BRLS_EINVAL */
+  int32_t nz, ny, nx; /* model grid (ny ignored in 2-D) */
+  int32_t nb;         /* absorbing cells on every face, >= 1 */
+  int32_t nt_max;     /* largest number of time samples of any shot */
+  int32_t nrec_max;   /* largest number of receivers of any shot */
+  int32_t q_max;      /* largest number of shots held at once */
+  double h;           /* grid spacing (m) */
+  double dt;          /* time step (s) */
+  double lambda;      /* damping of eq. 3, absolute */
+  uint32_t flags;     /* BRLS_DEVICE_PTRS */
+} brls_grid;
+
+typedef struct {
+  int64_t id;           /* caller's key, unique within the window */
+  int32_t sz, sy, sx;   /* source grid point, model grid (sy ignored in 2-D) */
+  int32_t nt, nrec;     /* 2 <= nt <= nt_max, 1 <= nrec <= nrec_max */
+  double f0;            /* Ricker peak frequency (Hz) */
+  const int32_t* rec;   /* host [nrec][3]: (z, y, x) model grid points */
+  const float* data;    /* observed data [nt][nrec] or NULL for zeros */
+} brls_shot;
+
+typedef struct {
+  int32_t iters;   /* CG iterations run */
+  double s0_norm;  /* ||A^T (d - A m0) - lambda m0|| at the start */
+  double s_norm;   /* same quantity at the end */
+  double r_norm;   /* ||d - A m|| at the end */
+  double seconds;  /* wall time of the call */
+} brls_stats;
+
+typedef struct {
+  char name[48];   /* kernel family, e.g. "born_step", "adjoint_step" */
+  int64_t launches;
+  double total_ms; /* summed durations between events bracketing each launch */
+} brls_kstat;
+
+/* Create a context for one velocity model.
+ * g: grid (copied). vel: host [nz][ny][nx] velocity in m/s, all > 0.
+ * stream: hipStream_t to order all work on; NULL gives the context a private
+ * stream that synchronises with the null stream (graphs cannot capture the
+ * null stream itself).
+ * Checks CFL stability of the scheme (v_max dt / h below the 2-D limit
+ * 0.5546 of the 8th-order stencil) and returns BRLS_EINVAL otherwise.
+ * Allocates the device state for q_max shots (see brls_memory_bytes). */
+int brls_open(const brls_grid* g, const float* vel, void* stream,
+              brls_ctx** out);
+
+/* Release every device and host resource of the context. NULL is a no-op. */
+void brls_close(brls_ctx* ctx);
+
+/* Message of the last failing call on ctx (or of the last failing brls_open
+ * when ctx is NULL). Valid until the next call on the same context. */
+const char* brls_last_error(const brls_ctx* ctx);
+
+/* Rank-one part of the paper's rank-K update (after eq. 10, Fig. 1): add one
+ * shot at the end of the window. Copies geometry and data; the background
+ * wavefield it needs is computed lazily by the next operator call.
+ * Errors: BRLS_EFULL, BRLS_EDUP, BRLS_EINVAL (positions, sizes),
+ * BRLS_ENONFINITE (data holds NaN/Inf). */
+int brls_update(brls_ctx* ctx, const brls_shot* shot);
+
+/* Rank-one part of the rank-K downdate: drop the shot with this id.
+ * Errors: BRLS_ENOSHOT. */
+int brls_downdate(brls_ctx* ctx, int64_t id);
+
+/* Replace the observed data of a shot already in the window ([nt][nrec]). */
+int brls_set_data(brls_ctx* ctx, int64_t id, const float* data);
+
+/* Ids of the window's shots in window order. ids may be NULL to only query
+ * the count; otherwise it has room for cap entries. */
+int brls_window(const brls_ctx* ctx, int64_t* ids, int32_t cap, int32_t* n);
+
+/* Total float count of the window's concatenated data (sum of nt * nrec). */
+int brls_window_data_size(const brls_ctx* ctx, int64_t* n);
+
+/* Solve eq. 10 on the current window by CG on the least-squares form,
+ * starting from the current image (eq. 11's warm start) and leaving the
+ * result as the current image. Stops after max_iter iterations or once
+ * ||A^T r - lambda m|| <= rtol * ||A^T d|| (rtol <= 0 disables this test).
+ * Vectors are float32; the CG scalars (alpha, beta, norms) are float64.
+ * An empty window or a zero gradient returns at once with iters = 0.
+ * stats may be NULL. Errors: BRLS_EBREAKDOWN, BRLS_ENONFINITE. */
+int brls_solve_window(brls_ctx* ctx, int32_t max_iter, double rtol,
+                      brls_stats* stats);
+
+/* Copy the current image [nz][ny][nx] out (synchronises the stream). */
+int brls_image(brls_ctx* ctx, float* out);
+
+/* Set the current image (e.g. resume, or an explicit start). */
+int brls_set_image(brls_ctx* ctx, const float* m);
+
+/* Eq. 1 without noise on the current window: d_out = A_w m (window data
+ * layout, brls_window_data_size floats). */
+int brls_apply_born(brls_ctx* ctx, const float* m, float* d_out);
+
+/* Eq. 2 on the current window: m_out = A_w^T d (sum over the window's shots,
+ * in window order). */
+int brls_apply_adjoint(brls_ctx* ctx, const float* d, float* m_out);
+
+/* Execution mode for the operator pair (BRLS_EXEC_*). Results agree across
+ * modes to rounding of the image reduction order. */
+int brls_set_exec(brls_ctx* ctx, int32_t mode);
+
+/* Tile shape of the stencil kernels: index into the compiled variants
+ * (brls_tile_count); -1 restores the default. brls_tile_info reports a
+ * variant's tile width tx, height tz and thread rows. */
+int brls_set_tile(brls_ctx* ctx, int32_t variant);
+int brls_tile_count(int32_t* n);
+int brls_tile_info(int32_t variant, int32_t* tx, int32_t* tz,
+                   int32_t* thread_rows);
+
+/* Shots one block handles in turn in batched modes (default 4). */
+int brls_set_shots_per_block(brls_ctx* ctx, int32_t per_block);
+int brls_get_tile(const brls_ctx* ctx, int32_t* variant, int32_t* per_block);
+
+/* Time every tile variant and shots-per-block choice on the current window
+ * (one Born and one adjoint application each, results discarded) and keep
+ * the fastest. Returns the chosen variant in *best. */
+int brls_autotune(brls_ctx* ctx, int32_t* best);
+
+/* Per-kernel timing with HIP events around every launch (adds small gaps
+ * between launches; off by default). brls_kernel_stats fills up to cap
+ * entries and resets the counters. */
+int brls_kernel_timing(brls_ctx* ctx, int32_t enable);
+int brls_kernel_stats(brls_ctx* ctx, brls_kstat* out, int32_t cap, int32_t* n);
+
+/* Device bytes held by the context. */
+int brls_memory_bytes(const brls_ctx* ctx, int64_t* bytes);
+
+/* Wait for all work queued on the context's stream. */
+int brls_sync(brls_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BRRLSM_H */

@@ -1,0 +1,267 @@
+"""Block-row recursive least-squares migration on MI355X.
+
+Python binding of the HIP library ``libbrrlsm.so`` (C ABI in
+``include/brrlsm.h``). The functions below carry the C names and only marshal
+arguments; all computation runs in the library's gfx950 kernels.
+
+Host arrays are numpy float32 / int32. With ``device=True`` the context
+takes device pointers: pass torch CUDA tensors (float32, contiguous), and the
+library orders its work on torch's current stream.
+
+Method: Kazemi & Sacchi, "Block row recursive least squares migration"
+(arXiv 1801.00819): eqs. 1-4 (Born de-migration A, migration A^T, damped
+least squares) and eqs. 10-11 (sliding windows of shots with rank-K update,
+downdate and warm-started CG).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (BRLS_EXEC_BATCHED, BRLS_EXEC_GRAPH,  # noqa: F401
+                   BRLS_EXEC_PLAIN, BrlsError)
+
+__all__ = [
+    "Context", "brls_open", "BrlsError", "BRLS_EXEC_PLAIN",
+    "BRLS_EXEC_BATCHED", "BRLS_EXEC_GRAPH",
+]
+
+
+def _ptr(a, device: bool):
+    if a is None:
+        return None
+    if device:
+        if not (hasattr(a, "is_cuda") and a.is_cuda):
+            raise TypeError("device context: pass a CUDA tensor")
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr())
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float32
+            and a.flags.c_contiguous):
+        raise TypeError("host context: pass a C-contiguous float32 ndarray")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Context:
+    """One velocity model, one window of shots, one image."""
+
+    def __init__(self, handle, nz, ny, nx, device):
+        self._h = handle
+        self.model_shape = (nz, ny, nx)
+        self.device = device
+        self._keep = []
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if self._h:
+            L.lib().brls_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        return L.check(rc, self._h)
+
+    def brls_update(self, id: int, src, rec: np.ndarray, nt: int, f0: float,
+                    data=None):
+        rec = np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, 3)
+        sh = L.brls_shot()
+        sh.id = int(id)
+        sh.sz, sh.sy, sh.sx = (int(v) for v in src)
+        sh.nt = int(nt)
+        sh.nrec = int(rec.shape[0])
+        sh.f0 = float(f0)
+        sh.rec = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if data is not None and not self.device:
+            data = np.ascontiguousarray(data, dtype=np.float32)
+        p = _ptr(data, self.device)
+        sh.data = p.value if p is not None else None
+        self._check(L.lib().brls_update(self._h, ctypes.byref(sh)))
+
+    update = brls_update
+
+    def brls_downdate(self, id: int):
+        self._check(L.lib().brls_downdate(self._h, int(id)))
+
+    downdate = brls_downdate
+
+    def brls_set_data(self, id: int, data):
+        if not self.device:
+            data = np.ascontiguousarray(data, dtype=np.float32)
+        self._check(L.lib().brls_set_data(self._h, int(id),
+                                          _ptr(data, self.device)))
+
+    set_data = brls_set_data
+
+    def brls_window(self) -> List[int]:
+        n = ctypes.c_int32()
+        self._check(L.lib().brls_window(self._h, None, 0, ctypes.byref(n)))
+        ids = (ctypes.c_int64 * max(n.value, 1))()
+        self._check(L.lib().brls_window(self._h, ids, n.value,
+                                        ctypes.byref(n)))
+        return list(ids[:n.value])
+
+    window = brls_window
+
+    def brls_window_data_size(self) -> int:
+        n = ctypes.c_int64()
+        self._check(L.lib().brls_window_data_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    window_data_size = brls_window_data_size
+
+    def brls_solve_window(self, max_iter: int, rtol: float = 0.0) -> dict:
+        st = L.brls_stats()
+        self._check(L.lib().brls_solve_window(self._h, int(max_iter),
+                                              float(rtol), ctypes.byref(st)))
+        return dict(iters=st.iters, s0_norm=st.s0_norm, s_norm=st.s_norm,
+                    r_norm=st.r_norm, seconds=st.seconds)
+
+    solve_window = brls_solve_window
+
+    def _model_out(self, out):
+        if out is not None:
+            return out
+        if self.device:
+            import torch
+            return torch.empty(self.model_shape, dtype=torch.float32,
+                               device="cuda")
+        return np.empty(self.model_shape, dtype=np.float32)
+
+    def brls_image(self, out=None):
+        out = self._model_out(out)
+        self._check(L.lib().brls_image(self._h, _ptr(out, self.device)))
+        return out
+
+    image = brls_image
+
+    def brls_set_image(self, m):
+        if not self.device:
+            m = np.ascontiguousarray(m, dtype=np.float32)
+        self._check(L.lib().brls_set_image(self._h, _ptr(m, self.device)))
+
+    set_image = brls_set_image
+
+    def brls_apply_born(self, m, out=None):
+        if not self.device:
+            m = np.ascontiguousarray(m, dtype=np.float32)
+        n = self.window_data_size()
+        if out is None:
+            if self.device:
+                import torch
+                out = torch.empty(n, dtype=torch.float32, device="cuda")
+            else:
+                out = np.empty(n, dtype=np.float32)
+        self._check(L.lib().brls_apply_born(self._h, _ptr(m, self.device),
+                                            _ptr(out, self.device)))
+        return out
+
+    apply_born = brls_apply_born
+
+    def brls_apply_adjoint(self, d, out=None):
+        if not self.device:
+            d = np.ascontiguousarray(d, dtype=np.float32)
+        out = self._model_out(out)
+        self._check(L.lib().brls_apply_adjoint(self._h, _ptr(d, self.device),
+                                               _ptr(out, self.device)))
+        return out
+
+    apply_adjoint = brls_apply_adjoint
+
+    def brls_set_exec(self, mode: int):
+        self._check(L.lib().brls_set_exec(self._h, int(mode)))
+
+    set_exec = brls_set_exec
+
+    def brls_set_tile(self, variant: int, shots_per_block: Optional[int] = None):
+        self._check(L.lib().brls_set_tile(self._h, int(variant)))
+        if shots_per_block is not None:
+            self._check(L.lib().brls_set_shots_per_block(
+                self._h, int(shots_per_block)))
+
+    set_tile = brls_set_tile
+
+    def brls_get_tile(self):
+        v, pb = ctypes.c_int32(), ctypes.c_int32()
+        self._check(L.lib().brls_get_tile(self._h, ctypes.byref(v),
+                                          ctypes.byref(pb)))
+        return v.value, pb.value
+
+    get_tile = brls_get_tile
+
+    def brls_autotune(self) -> int:
+        best = ctypes.c_int32()
+        self._check(L.lib().brls_autotune(self._h, ctypes.byref(best)))
+        return best.value
+
+    autotune = brls_autotune
+
+    def brls_kernel_timing(self, enable: bool):
+        self._check(L.lib().brls_kernel_timing(self._h, int(bool(enable))))
+
+    kernel_timing = brls_kernel_timing
+
+    def brls_kernel_stats(self) -> dict:
+        arr = (L.brls_kstat * 16)()
+        n = ctypes.c_int32()
+        self._check(L.lib().brls_kernel_stats(self._h, arr, 16,
+                                              ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms)
+                for i in range(min(n.value, 16))}
+
+    kernel_stats = brls_kernel_stats
+
+    def brls_memory_bytes(self) -> int:
+        n = ctypes.c_int64()
+        self._check(L.lib().brls_memory_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    memory_bytes = brls_memory_bytes
+
+    def brls_sync(self):
+        self._check(L.lib().brls_sync(self._h))
+
+    sync = brls_sync
+
+
+def brls_open(ndim: int, nz: int, ny: int, nx: int, nb: int, nt_max: int,
+              nrec_max: int, q_max: int, h: float, dt: float, lam: float,
+              vel: np.ndarray, device: bool = False, stream=None) -> Context:
+    """Open a context (velocity ``vel`` [nz][ny][nx], m/s, host array).
+
+    ``stream``: a hipStream_t as int; with ``device=True`` and no stream given,
+    torch's current stream is used."""
+    g = L.brls_grid()
+    g.ndim, g.nz, g.ny, g.nx, g.nb = ndim, nz, ny, nx, nb
+    g.nt_max, g.nrec_max, g.q_max = nt_max, nrec_max, q_max
+    g.h, g.dt, g.lambda_ = float(h), float(dt), float(lam)
+    g.flags = L.BRLS_DEVICE_PTRS if device else 0
+    if device and stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    v = np.ascontiguousarray(vel, dtype=np.float32)
+    h_ = ctypes.c_void_p()
+    rc = L.lib().brls_open(ctypes.byref(g), v.ctypes.data,
+                           ctypes.c_void_p(stream) if stream else None,
+                           ctypes.byref(h_))
+    L.check(rc, None)
+    return Context(h_, nz, ny if ndim == 3 else 1, nx, device)
+
+
+def tile_variants():
+    n = ctypes.c_int32()
+    L.check(L.lib().brls_tile_count(ctypes.byref(n)))
+    out = []
+    for v in range(n.value):
+        tx, tz, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().brls_tile_info(v, ctypes.byref(tx), ctypes.byref(tz),
+                                       ctypes.byref(r)))
+        out.append((tx.value, tz.value, r.value))
+    return out

@@ -1,0 +1,164 @@
+// Vector kernels of the CG solver: fills, axpy-type updates and dot
+// products of float32 vectors accumulated in float64.
+//
+// Dot products run in two fixed-order stages (kDotBlocks per-block partial
+// sums, then a single block), so a result does not depend on scheduling and
+// repeated runs are bitwise identical.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace brls {
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Block-wide float64 sum in LDS (256 threads), result in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ void __launch_bounds__(256)
+    k_dot_partial(const float* a, const float* b, int64_t n, double* part) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)a[i] * (double)b[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256)
+    k_sum_final(const double* part, int np, double* out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+__global__ void k_axpy(float* y, const float* x, double alpha, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)((double)y[i] + alpha * (double)x[i]);
+}
+
+__global__ void k_xpby(float* p, const float* s, double beta, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (float)((double)s[i] + beta * (double)p[i]);
+}
+
+__global__ void k_sub(float* r, const float* d, const float* q, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = d[i] - q[i];
+}
+
+__global__ void __launch_bounds__(256)
+    k_grad_norm(float* s, const float* g, const float* m, double lambda,
+                int64_t n, double* part) {
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = (float)((double)g[i] - lambda * (double)m[i]);
+    s[i] = v;
+    acc += (double)v * (double)v;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_nonfinite(const float* x, int64_t n, int* flag) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+static int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, int64_t n,
+                      double* partial, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, a, b,
+                     n, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial,
+                     kDotBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(float* y, const float* x, double alpha, int64_t n,
+                       hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, st, y, x, alpha,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby(float* p, const float* s, double beta, int64_t n,
+                       hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xpby, dim3(grid_for(n)), dim3(256), 0, st, p, s, beta,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub(float* r, const float* d, const float* q, int64_t n,
+                      hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, st, r, d, q, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_norm(float* s, const float* g, const float* m,
+                            double lambda, int64_t n, double* partial,
+                            double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_norm, dim3(kDotBlocks), dim3(256), 0, st, s, g, m,
+                     lambda, n, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial,
+                     kDotBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const float* x, int64_t n, int* flag,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(n)), dim3(256), 0, st, x, n,
+                     flag);
+  return hipGetLastError();
+}
+
+}  // namespace brls

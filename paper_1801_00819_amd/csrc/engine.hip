@@ -1,0 +1,1031 @@
+// Host engine and C ABI of the library: window of shots (update/downdate),
+// background wavefields, the operator pair A / A^T over the window in three
+// execution modes, and the damped CG solve of each window.
+//
+// Method: Kazemi & Sacchi, "Block row recursive least squares migration"
+// (arXiv 1801.00819). Each window solves min ||A_w m - d_w||^2 + lambda||m||^2
+// (eq. 10, the windowed form of eq. 3) by CG on the least-squares form,
+// warm-started from the previous window's image (eq. 11); windows change by
+// adding new shots and removing the oldest (rank-K update and downdate).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "brrlsm.h"
+#include "kernels.h"
+#include "layout.h"
+
+using namespace brls;
+
+namespace {
+
+// 8th-order central second-derivative weights (offsets 1..4); the
+// difference-form stencil needs no centre weight.
+constexpr double kW1 = 8.0 / 5.0, kW2 = -1.0 / 5.0, kW3 = 8.0 / 315.0,
+                 kW4 = -1.0 / 560.0;
+// Largest stable Courant number v dt / h in 2-D for this stencil with the
+// second-order time step: the symbol of h^2 L per axis peaks at
+// S = 205/72 + 2 (8/5 + 1/5 + 8/315 + 1/560) at the Nyquist wavenumber, and
+// leapfrog needs C^2 * 2S <= 4, i.e. C <= 2 / sqrt(2 S).
+constexpr double kCfl2D = 0.5546;
+
+thread_local std::string g_open_error;
+
+struct Slot {
+  bool used = false;
+  int64_t id = 0;
+  int64_t seq = 0;
+  int nt = 0, nrec = 0;
+  int sz = 0, sx = 0;
+  double f0 = 0.0;
+  std::vector<int32_t> rec;  // host copy (z, y, x)
+  bool bg_ready = false;
+  float* fields = nullptr;   // u0 | u1 | v
+  float* d2 = nullptr;       // [nt_max-1][nz][nx]
+  float* wav = nullptr;      // [nt_max]
+  int* rptr = nullptr;       // [ntiles_max + 1]
+  int2* rent = nullptr;      // [nrec_max]
+  int* rsidx = nullptr;      // [nrec_max]
+  int64_t dat_off = 0;
+};
+
+struct Timer {
+  int kind;
+  hipEvent_t a, b;
+};
+
+enum TimerKind { kTBackground, kTBorn, kTAdjoint, kTBornGraph, kTAdjGraph,
+                 kTNumKinds };
+const char* kTimerNames[kTNumKinds] = {"background_step", "born_step",
+                                       "adjoint_step", "born_graph",
+                                       "adjoint_graph"};
+
+using GraphKey = std::tuple<int, int, int, int, int>;  // op, nshots, pb, var, nt
+
+}  // namespace
+
+struct brls_ctx {
+  brls_grid g{};
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  Geo2D geo{};
+  int variant = 0;
+  int per_block = 4;
+  int exec = BRLS_EXEC_GRAPH;
+  int rows_alloc = 0;
+  int64_t fs = 0;      // floats per field buffer
+  int64_t mplane = 0;  // model points
+  int64_t seg = 0;     // floats per shot segment of data vectors
+  int ntiles_max = 0;
+  float* wp = nullptr;
+  float* fields_all = nullptr;
+  float *m = nullptr, *p = nullptr, *s = nullptr, *gbuf = nullptr,
+        *born_in = nullptr;
+  double* acc = nullptr;
+  float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr;
+  double *partial = nullptr, *scal = nullptr;
+  int* flag = nullptr;
+  ShotDev* tab_dev = nullptr;
+  ShotDev* bgtab_dev = nullptr;
+  bool tab_dirty = true;
+  std::vector<Slot> slots;
+  std::vector<int> order;  // slot indices in window order
+  int64_t next_seq = 0;
+  std::string err;
+  bool timing = false;
+  std::vector<Timer> timers;
+  std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  int64_t mem_bytes = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int fail(brls_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_open_error = buf;
+  return code;
+}
+
+#define HIPCHECK(ctx, call)                                                  \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(ctx, BRLS_EDEVICE, "%s: %s (%s:%d)", #call,                \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                \
+  } while (0)
+
+template <class T>
+int dalloc(brls_ctx* c, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  const size_t bytes = (size_t)count * sizeof(T);
+  if (hipMalloc((void**)p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(c, BRLS_ENOMEM, "device allocation of %zu bytes failed",
+                bytes);
+  }
+  c->allocs.push_back(*p);
+  c->mem_bytes += (int64_t)bytes;
+  return BRLS_OK;
+}
+
+bool dev_ptrs(const brls_ctx* c) { return (c->g.flags & BRLS_DEVICE_PTRS); }
+
+hipMemcpyKind in_kind(const brls_ctx* c) {
+  return dev_ptrs(c) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind out_kind(const brls_ctx* c) {
+  return dev_ptrs(c) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+void set_variant_geo(brls_ctx* c, int v) {
+  const TileShape ts = tile_shape(v);
+  Geo2D& g = c->geo;
+  g.ntx = (g.px - g.x_org + ts.tx - 1) / ts.tx;
+  g.ntz = (g.pz + ts.tz - 1) / ts.tz;
+  g.ntiles = g.ntx * g.ntz;
+  c->variant = v;
+}
+
+// Per-tile receiver lists of one slot for the current tile shape.
+int build_receiver_tiles(brls_ctx* c, Slot& sl) {
+  const TileShape ts = tile_shape(c->variant);
+  const Geo2D& g = c->geo;
+  std::vector<int> cnt(g.ntiles + 1, 0), tileof(sl.nrec), loc(sl.nrec);
+  for (int j = 0; j < sl.nrec; ++j) {
+    const int pz = sl.rec[3 * j] + g.nb, px = sl.rec[3 * j + 2] + g.nb;
+    const int tzi = pz / ts.tz, txi = (px - g.x_org) / ts.tx;
+    tileof[j] = tzi * g.ntx + txi;
+    loc[j] = (pz - tzi * ts.tz) * ts.tx + (px - g.x_org - txi * ts.tx);
+    cnt[tileof[j] + 1]++;
+  }
+  for (int t = 0; t < g.ntiles; ++t) cnt[t + 1] += cnt[t];
+  std::vector<int2> ent(std::max(sl.nrec, 1));
+  std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
+  for (int j = 0; j < sl.nrec; ++j) {
+    int2 e;
+    e.x = loc[j];
+    e.y = j;
+    ent[fillp[tileof[j]]++] = e;
+  }
+  HIPCHECK(c, hipMemcpyAsync(sl.rptr, cnt.data(), sizeof(int) * cnt.size(),
+                             hipMemcpyHostToDevice, c->st));
+  HIPCHECK(c, hipMemcpyAsync(sl.rent, ent.data(), sizeof(int2) * sl.nrec,
+                             hipMemcpyHostToDevice, c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+ShotDev shot_dev(const brls_ctx* c, const Slot& sl) {
+  ShotDev d{};
+  d.u0 = sl.fields;
+  d.u1 = sl.fields + c->fs;
+  d.v = sl.fields + 2 * c->fs;
+  d.d2 = sl.d2;
+  d.rptr = sl.rptr;
+  d.rent = sl.rent;
+  d.rsidx = sl.rsidx;
+  d.wav = sl.wav;
+  d.dat_off = sl.dat_off;
+  d.nt = sl.nt;
+  d.nrec = sl.nrec;
+  d.src_z = sl.sz + c->geo.nb;
+  d.src_x = sl.sx + c->geo.nb;
+  return d;
+}
+
+void rebuild_order(brls_ctx* c) {
+  c->order.clear();
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (c->slots[i].used) c->order.push_back(i);
+  std::sort(c->order.begin(), c->order.end(), [c](int a, int b) {
+    return c->slots[a].seq < c->slots[b].seq;
+  });
+  c->tab_dirty = true;
+}
+
+int ensure_tab(brls_ctx* c) {
+  if (!c->tab_dirty) return BRLS_OK;
+  std::vector<ShotDev> tab;
+  for (int i : c->order) tab.push_back(shot_dev(c, c->slots[i]));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  if (!tab.empty())
+    HIPCHECK(c, hipMemcpy(c->tab_dev, tab.data(), sizeof(ShotDev) * tab.size(),
+                          hipMemcpyHostToDevice));
+  c->tab_dirty = false;
+  return BRLS_OK;
+}
+
+int nt_max_of(const brls_ctx* c, const std::vector<int>& idx) {
+  int n = 0;
+  for (int i : idx) n = std::max(n, c->slots[i].nt);
+  return n;
+}
+
+// --- timing ---------------------------------------------------------------
+int timed_begin(brls_ctx* c, int kind, Timer* t) {
+  if (!c->timing) return BRLS_OK;
+  t->kind = kind;
+  HIPCHECK(c, hipEventCreate(&t->a));
+  HIPCHECK(c, hipEventCreate(&t->b));
+  HIPCHECK(c, hipEventRecord(t->a, c->st));
+  return BRLS_OK;
+}
+int timed_end(brls_ctx* c, Timer* t) {
+  if (!c->timing) return BRLS_OK;
+  HIPCHECK(c, hipEventRecord(t->b, c->st));
+  c->timers.push_back(*t);
+  return BRLS_OK;
+}
+
+StepArgs base_args(const brls_ctx* c) {
+  StepArgs a{};
+  a.g = c->geo;
+  a.wp = c->wp;
+  return a;
+}
+
+// One time step over `nshots` table entries starting at `tab`.
+int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
+         int per_block, const float* pm, float* dat, double* acc) {
+  StepArgs a = base_args(c);
+  a.tab = tab;
+  a.nshots = nshots;
+  a.per_block = per_block;
+  a.ngroups = (nshots + per_block - 1) / per_block;
+  a.n = n;
+  a.pm = pm;
+  a.dat = dat;
+  a.acc = acc;
+  Timer t;
+  int rc = timed_begin(c, mode == kBackground ? kTBackground
+                          : mode == kBorn     ? kTBorn
+                                              : kTAdjoint,
+                       &t);
+  if (rc) return rc;
+  HIPCHECK(c, launch_step2d(c->variant, mode, a, c->st));
+  return timed_end(c, &t);
+}
+
+int zero_fields(brls_ctx* c) {
+  HIPCHECK(c, launch_fill_f32(c->fields_all,
+                              (int64_t)c->g.q_max * 3 * c->fs, 0.f, c->st));
+  return BRLS_OK;
+}
+
+// Background wavefields (and Born-source caches) of shots that lack them.
+int ensure_backgrounds(brls_ctx* c) {
+  std::vector<int> todo;
+  for (int i : c->order)
+    if (!c->slots[i].bg_ready) todo.push_back(i);
+  if (todo.empty()) return BRLS_OK;
+  std::vector<ShotDev> tab;
+  for (int i : todo) tab.push_back(shot_dev(c, c->slots[i]));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  HIPCHECK(c, hipMemcpy(c->bgtab_dev, tab.data(), sizeof(ShotDev) * tab.size(),
+                        hipMemcpyHostToDevice));
+  int rc;
+  for (int i : todo) {
+    Slot& sl = c->slots[i];
+    HIPCHECK(c, launch_fill_f32(sl.fields, 3 * c->fs, 0.f, c->st));
+  }
+  const int ntm = nt_max_of(c, todo);
+  const int nsh = (int)todo.size();
+  if (c->exec == BRLS_EXEC_PLAIN) {
+    for (int k = 0; k < nsh; ++k)
+      for (int n = 0; n + 1 < c->slots[todo[k]].nt; ++n)
+        if ((rc = step(c, kBackground, n, c->bgtab_dev + k, 1, 1, nullptr,
+                       nullptr, nullptr)))
+          return rc;
+  } else {
+    for (int n = 0; n + 1 < ntm; ++n)
+      if ((rc = step(c, kBackground, n, c->bgtab_dev, nsh,
+                     std::min(c->per_block, nsh), nullptr, nullptr, nullptr)))
+        return rc;
+  }
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  for (int i : todo) c->slots[i].bg_ready = true;
+  return BRLS_OK;
+}
+
+// Kernel sequence of one operator application (also what a graph captures).
+int enqueue_born(brls_ctx* c, int batched) {
+  const int nsh = (int)c->order.size();
+  const int ntm = nt_max_of(c, c->order);
+  int rc;
+  if ((rc = zero_fields(c))) return rc;
+  if (!batched) {
+    for (int k = 0; k < nsh; ++k)
+      for (int n = 0; n + 1 < c->slots[c->order[k]].nt; ++n)
+        if ((rc = step(c, kBorn, n, c->tab_dev + k, 1, 1, c->born_in, c->q,
+                       nullptr)))
+          return rc;
+  } else {
+    const int pb = std::min(c->per_block, nsh);
+    for (int n = 0; n + 1 < ntm; ++n)
+      if ((rc = step(c, kBorn, n, c->tab_dev, nsh, pb, c->born_in, c->q,
+                     nullptr)))
+        return rc;
+  }
+  HIPCHECK(c, launch_born_last(c->tab_dev, nsh, c->g.nrec_max, c->q, c->st));
+  return BRLS_OK;
+}
+
+int enqueue_adjoint(brls_ctx* c, int batched) {
+  const int nsh = (int)c->order.size();
+  const int ntm = nt_max_of(c, c->order);
+  const int pb = batched ? std::min(c->per_block, nsh) : 1;
+  const int ngroups = batched ? (nsh + pb - 1) / pb : 1;
+  int rc;
+  if ((rc = zero_fields(c))) return rc;
+  HIPCHECK(c, launch_fill_f64(c->acc, ngroups * c->mplane, 0.0, c->st));
+  if (!batched) {
+    for (int k = 0; k < nsh; ++k)
+      for (int n = c->slots[c->order[k]].nt - 1; n >= 1; --n)
+        if ((rc = step(c, kAdjoint, n, c->tab_dev + k, 1, 1, nullptr,
+                       c->dscr, c->acc)))
+          return rc;
+  } else {
+    for (int n = ntm - 1; n >= 1; --n)
+      if ((rc = step(c, kAdjoint, n, c->tab_dev, nsh, pb, nullptr, c->dscr,
+                     c->acc)))
+        return rc;
+  }
+  HIPCHECK(c, launch_adj_finalize(c->acc, ngroups, c->geo, c->wp, c->gbuf,
+                                  c->st));
+  return BRLS_OK;
+}
+
+int run_op(brls_ctx* c, int op) {
+  int rc;
+  if ((rc = ensure_tab(c)) || (rc = ensure_backgrounds(c)) ||
+      (rc = ensure_tab(c)))
+    return rc;
+  if (c->order.empty()) return BRLS_OK;
+  if (c->exec != BRLS_EXEC_GRAPH)
+    return op == kBorn ? enqueue_born(c, c->exec == BRLS_EXEC_BATCHED)
+                       : enqueue_adjoint(c, c->exec == BRLS_EXEC_BATCHED);
+  const int nsh = (int)c->order.size();
+  const GraphKey key(op, nsh, std::min(c->per_block, nsh), c->variant,
+                     nt_max_of(c, c->order));
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    const bool was_timing = c->timing;
+    c->timing = false;
+    HIPCHECK(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    rc = op == kBorn ? enqueue_born(c, 1) : enqueue_adjoint(c, 1);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->st, &graph);
+    c->timing = was_timing;
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess)
+      return fail(c, BRLS_EDEVICE, "graph capture failed: %s",
+                  hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    HIPCHECK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    it = c->graphs.emplace(key, std::make_pair(graph, exec)).first;
+  }
+  Timer t;
+  if ((rc = timed_begin(c, op == kBorn ? kTBornGraph : kTAdjGraph, &t)))
+    return rc;
+  HIPCHECK(c, hipGraphLaunch(it->second.second, c->st));
+  return timed_end(c, &t);
+}
+
+void drop_graphs(brls_ctx* c) {
+  for (auto& kv : c->graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  c->graphs.clear();
+}
+
+int born_of(brls_ctx* c, const float* model_dev) {
+  if (model_dev != c->born_in)
+    HIPCHECK(c, hipMemcpyAsync(c->born_in, model_dev, c->mplane * 4,
+                               hipMemcpyDeviceToDevice, c->st));
+  return run_op(c, kBorn);
+}
+
+int adjoint_of(brls_ctx* c, const float* data_dev) {
+  if (data_dev != c->dscr)
+    HIPCHECK(c, hipMemcpyAsync(c->dscr, data_dev,
+                               (size_t)c->g.q_max * c->seg * 4,
+                               hipMemcpyDeviceToDevice, c->st));
+  return run_op(c, kAdjoint);
+}
+
+int read_scalars(brls_ctx* c, double* out, int n) {
+  HIPCHECK(c, hipMemcpyAsync(out, c->scal, sizeof(double) * n,
+                             hipMemcpyDeviceToHost, c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int find_slot(const brls_ctx* c, int64_t id) {
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (c->slots[i].used && c->slots[i].id == id) return i;
+  return -1;
+}
+
+int check_finite(brls_ctx* c, const float* dev, int64_t n, bool* ok) {
+  HIPCHECK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->st));
+  HIPCHECK(c, launch_nonfinite(dev, n, c->flag, c->st));
+  int h = 0;
+  HIPCHECK(c, hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost,
+                             c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  *ok = (h == 0);
+  return BRLS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int brls_open(const brls_grid* gin, const float* vel, void* stream,
+              brls_ctx** out) {
+  if (!out) return fail(nullptr, BRLS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!gin || !vel) return fail(nullptr, BRLS_EINVAL, "grid or vel is NULL");
+  const brls_grid g = *gin;
+  if (g.ndim != 2)
+    return fail(nullptr, BRLS_EINVAL, "ndim %d not supported (2-D only)",
+                g.ndim);
+  if (g.nz < 1 || g.nx < 1 || g.nb < 1 || g.nt_max < 2 || g.nrec_max < 1 ||
+      g.q_max < 1 || !(g.h > 0) || !(g.dt > 0) || !(g.lambda >= 0))
+    return fail(nullptr, BRLS_EINVAL, "invalid grid sizes or spacing");
+  const int64_t mpts = (int64_t)g.nz * g.nx;
+  double vmax = 0.0;
+  for (int64_t i = 0; i < mpts; ++i) {
+    if (!(vel[i] > 0.f) || !std::isfinite(vel[i]))
+      return fail(nullptr, BRLS_EINVAL, "velocity must be finite and > 0");
+    vmax = std::max(vmax, (double)vel[i]);
+  }
+  if (vmax * g.dt / g.h > kCfl2D)
+    return fail(nullptr, BRLS_EINVAL,
+                "unstable: v_max dt / h = %.4f exceeds %.4f",
+                vmax * g.dt / g.h, kCfl2D);
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(nullptr, BRLS_EDEVICE, "no HIP device");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, BRLS_EDEVICE,
+                "library is built for gfx950, device is %s", prop.gcnArchName);
+
+  brls_ctx* c = new brls_ctx();
+  c->g = g;
+  c->st = (hipStream_t)stream;
+  if (!c->st) {
+    // The null stream cannot be captured into a graph: use a private stream
+    // that still synchronises with the null stream (blocking, default
+    // priority).
+    if (hipStreamCreate(&c->st) != hipSuccess) {
+      delete c;
+      return fail(nullptr, BRLS_EDEVICE, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  c->device = dev;
+  Geo2D& geo = c->geo;
+  geo.nz = g.nz;
+  geo.nx = g.nx;
+  geo.nb = g.nb;
+  geo.pz = g.nz + 2 * g.nb;
+  geo.px = g.nx + 2 * g.nb;
+  geo.x_org = (g.nb % 32 == 0) ? 0 : (g.nb % 32) - 32;
+  geo.xoff = 32 - geo.x_org;
+  geo.pitch = round_up(geo.xoff + round_up(geo.px - geo.x_org, 128) + kGhost,
+                       32);
+  c->rows_alloc = round_up(geo.pz, 64) + 2 * kGhost;
+  c->fs = (int64_t)c->rows_alloc * geo.pitch;
+  const double eta_max = 3.0 * vmax * std::log(1000.0) / (2.0 * g.nb * g.h);
+  geo.eta_scale = (float)(eta_max * g.dt / 2.0 / ((double)g.nb * g.nb));
+  geo.w.c1 = (float)kW1;
+  geo.w.c2 = (float)kW2;
+  geo.w.c3 = (float)kW3;
+  geo.w.c4 = (float)kW4;
+  c->ntiles_max = 0;
+  for (int v = 0; v < tile_shape_count(); ++v) {
+    set_variant_geo(c, v);
+    c->ntiles_max = std::max(c->ntiles_max, geo.ntiles);
+  }
+  set_variant_geo(c, 0);
+  c->mplane = mpts;
+  c->seg = round_up((int)std::min<int64_t>((int64_t)g.nt_max * g.nrec_max,
+                                           (int64_t)1 << 30),
+                    64);
+
+  int rc = BRLS_OK;
+#define ALLOC(ptr, n)                               \
+  if ((rc = dalloc(c, &(ptr), (n))) != BRLS_OK) {   \
+    g_open_error = c->err;                          \
+    brls_close(c);                                  \
+    return rc;                                      \
+  }
+  ALLOC(c->wp, c->fs);
+  ALLOC(c->fields_all, (int64_t)g.q_max * 3 * c->fs);
+  ALLOC(c->m, mpts);
+  ALLOC(c->p, mpts);
+  ALLOC(c->s, mpts);
+  ALLOC(c->gbuf, mpts);
+  ALLOC(c->born_in, mpts);
+  ALLOC(c->acc, (int64_t)g.q_max * mpts);
+  ALLOC(c->dobs, (int64_t)g.q_max * c->seg);
+  ALLOC(c->r, (int64_t)g.q_max * c->seg);
+  ALLOC(c->q, (int64_t)g.q_max * c->seg);
+  ALLOC(c->dscr, (int64_t)g.q_max * c->seg);
+  ALLOC(c->partial, kDotBlocks);
+  ALLOC(c->scal, 16);
+  ALLOC(c->flag, 1);
+  ALLOC(c->tab_dev, g.q_max);
+  ALLOC(c->bgtab_dev, g.q_max);
+  c->slots.resize(g.q_max);
+  for (int i = 0; i < g.q_max; ++i) {
+    Slot& sl = c->slots[i];
+    sl.fields = c->fields_all + (int64_t)i * 3 * c->fs;
+    sl.dat_off = (int64_t)i * c->seg;
+    ALLOC(sl.d2, (int64_t)(g.nt_max - 1) * mpts);
+    ALLOC(sl.wav, g.nt_max);
+    ALLOC(sl.rptr, c->ntiles_max + 1);
+    ALLOC(sl.rent, g.nrec_max);
+    ALLOC(sl.rsidx, g.nrec_max);
+  }
+#undef ALLOC
+  // W' = v^2 dt^2 / h^2 on the padded grid (velocity edge-replicated)
+  std::vector<float> wh((size_t)c->fs, 0.f);
+  const double s2 = g.dt * g.dt / (g.h * g.h);
+  for (int z = 0; z < geo.pz; ++z)
+    for (int x = 0; x < geo.px; ++x) {
+      const int mz = std::min(std::max(z - g.nb, 0), g.nz - 1);
+      const int mx = std::min(std::max(x - g.nb, 0), g.nx - 1);
+      const double v = vel[(int64_t)mz * g.nx + mx];
+      wh[sidx2(geo, z, x)] = (float)(v * v * s2);
+    }
+  auto init = [&]() -> int {
+    HIPCHECK(c, hipMemcpy(c->wp, wh.data(), sizeof(float) * wh.size(),
+                          hipMemcpyHostToDevice));
+    HIPCHECK(c, launch_fill_f32(c->fields_all, (int64_t)g.q_max * 3 * c->fs,
+                                0.f, c->st));
+    HIPCHECK(c, launch_fill_f32(c->m, mpts, 0.f, c->st));
+    for (float* v : {c->dobs, c->r, c->q, c->dscr})
+      HIPCHECK(c, launch_fill_f32(v, (int64_t)g.q_max * c->seg, 0.f, c->st));
+    HIPCHECK(c, hipStreamSynchronize(c->st));
+    return BRLS_OK;
+  };
+  if ((rc = init()) != BRLS_OK) {
+    g_open_error = c->err;
+    brls_close(c);
+    return rc;
+  }
+  *out = c;
+  return BRLS_OK;
+}
+
+void brls_close(brls_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  drop_graphs(c);
+  for (auto& t : c->timers) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->own_stream) (void)hipStreamDestroy(c->st);
+  delete c;
+}
+
+const char* brls_last_error(const brls_ctx* c) {
+  return c ? c->err.c_str() : g_open_error.c_str();
+}
+
+int brls_update(brls_ctx* c, const brls_shot* sh) {
+  if (!c || !sh) return fail(c, BRLS_EINVAL, "NULL argument");
+  if (find_slot(c, sh->id) >= 0)
+    return fail(c, BRLS_EDUP, "shot %lld already in the window",
+                (long long)sh->id);
+  int free_i = -1;
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (!c->slots[i].used) {
+      free_i = i;
+      break;
+    }
+  if (free_i < 0)
+    return fail(c, BRLS_EFULL, "window already holds q_max = %d shots",
+                c->g.q_max);
+  if (sh->nt < 2 || sh->nt > c->g.nt_max || sh->nrec < 1 ||
+      sh->nrec > c->g.nrec_max || !(sh->f0 > 0) || !sh->rec)
+    return fail(c, BRLS_EINVAL, "shot %lld: bad nt, nrec, f0 or receivers",
+                (long long)sh->id);
+  if (sh->sz < 0 || sh->sz >= c->g.nz || sh->sx < 0 || sh->sx >= c->g.nx)
+    return fail(c, BRLS_EINVAL, "shot %lld: source outside the model",
+                (long long)sh->id);
+  for (int j = 0; j < sh->nrec; ++j) {
+    const int z = sh->rec[3 * j], x = sh->rec[3 * j + 2];
+    if (z < 0 || z >= c->g.nz || x < 0 || x >= c->g.nx)
+      return fail(c, BRLS_EINVAL, "shot %lld: receiver %d outside the model",
+                  (long long)sh->id, j);
+  }
+  Slot& sl = c->slots[free_i];
+  const int64_t nd = (int64_t)sh->nt * sh->nrec;
+  float* seg = c->dobs + sl.dat_off;
+  HIPCHECK(c, launch_fill_f32(seg, c->seg, 0.f, c->st));
+  if (sh->data) {
+    HIPCHECK(c, hipMemcpyAsync(seg, sh->data, nd * 4, in_kind(c), c->st));
+    bool ok = true;
+    int rc = check_finite(c, seg, nd, &ok);
+    if (rc) return rc;
+    if (!ok) {
+      HIPCHECK(c, launch_fill_f32(seg, c->seg, 0.f, c->st));
+      return fail(c, BRLS_ENONFINITE, "shot %lld: data hold NaN or Inf",
+                  (long long)sh->id);
+    }
+  }
+  sl.id = sh->id;
+  sl.nt = sh->nt;
+  sl.nrec = sh->nrec;
+  sl.sz = sh->sz;
+  sl.sx = sh->sx;
+  sl.f0 = sh->f0;
+  sl.rec.assign(sh->rec, sh->rec + 3 * sh->nrec);
+  // h^2 * Ricker(f0), delay 1.5/f0: the point source of strength h^d f(t)
+  // scaled to the W' = v^2 dt^2 / h^2 of the kernels.
+  std::vector<float> wav(sh->nt);
+  const double t0 = 1.5 / sh->f0, pi = 3.14159265358979323846;
+  for (int n = 0; n < sh->nt; ++n) {
+    const double t = n * c->g.dt - t0;
+    const double a = pi * pi * sh->f0 * sh->f0 * t * t;
+    wav[n] = (float)(c->g.h * c->g.h * (1.0 - 2.0 * a) * std::exp(-a));
+  }
+  std::vector<int> rs(sh->nrec);
+  for (int j = 0; j < sh->nrec; ++j)
+    rs[j] = (int)sidx2(c->geo, sl.rec[3 * j] + c->geo.nb,
+                       sl.rec[3 * j + 2] + c->geo.nb);
+  HIPCHECK(c, hipMemcpyAsync(sl.wav, wav.data(), 4 * wav.size(),
+                             hipMemcpyHostToDevice, c->st));
+  HIPCHECK(c, hipMemcpyAsync(sl.rsidx, rs.data(), 4 * rs.size(),
+                             hipMemcpyHostToDevice, c->st));
+  int rc = build_receiver_tiles(c, sl);  // synchronises
+  if (rc) return rc;
+  sl.used = true;
+  sl.bg_ready = false;
+  sl.seq = c->next_seq++;
+  rebuild_order(c);
+  return BRLS_OK;
+}
+
+int brls_downdate(brls_ctx* c, int64_t id) {
+  if (!c) return BRLS_EINVAL;
+  const int i = find_slot(c, id);
+  if (i < 0)
+    return fail(c, BRLS_ENOSHOT, "no shot %lld in the window", (long long)id);
+  Slot& sl = c->slots[i];
+  for (float* v : {c->dobs, c->r, c->q, c->dscr})
+    HIPCHECK(c, launch_fill_f32(v + sl.dat_off, c->seg, 0.f, c->st));
+  sl.used = false;
+  sl.bg_ready = false;
+  rebuild_order(c);
+  return BRLS_OK;
+}
+
+int brls_set_data(brls_ctx* c, int64_t id, const float* data) {
+  if (!c || !data) return fail(c, BRLS_EINVAL, "NULL argument");
+  const int i = find_slot(c, id);
+  if (i < 0)
+    return fail(c, BRLS_ENOSHOT, "no shot %lld in the window", (long long)id);
+  Slot& sl = c->slots[i];
+  const int64_t nd = (int64_t)sl.nt * sl.nrec;
+  HIPCHECK(c, hipMemcpyAsync(c->dscr, data, nd * 4, in_kind(c), c->st));
+  bool ok = true;
+  int rc = check_finite(c, c->dscr, nd, &ok);
+  if (rc) return rc;
+  if (!ok) return fail(c, BRLS_ENONFINITE, "data hold NaN or Inf");
+  HIPCHECK(c, hipMemcpyAsync(c->dobs + sl.dat_off, c->dscr, nd * 4,
+                             hipMemcpyDeviceToDevice, c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_window(const brls_ctx* c, int64_t* ids, int32_t cap, int32_t* n) {
+  if (!c || !n) return BRLS_EINVAL;
+  *n = (int32_t)c->order.size();
+  if (ids)
+    for (int k = 0; k < *n && k < cap; ++k) ids[k] = c->slots[c->order[k]].id;
+  return BRLS_OK;
+}
+
+int brls_window_data_size(const brls_ctx* c, int64_t* n) {
+  if (!c || !n) return BRLS_EINVAL;
+  int64_t s = 0;
+  for (int i : c->order) s += (int64_t)c->slots[i].nt * c->slots[i].nrec;
+  *n = s;
+  return BRLS_OK;
+}
+
+int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
+                      brls_stats* stats) {
+  if (!c) return BRLS_EINVAL;
+  const auto t_start = std::chrono::steady_clock::now();
+  brls_stats st{};
+  auto finish = [&](int code) {
+    st.seconds = std::chrono::duration<double>(
+                     std::chrono::steady_clock::now() - t_start)
+                     .count();
+    if (stats) *stats = st;
+    return code;
+  };
+  if (c->order.empty()) return finish(BRLS_OK);
+  const double lam = c->g.lambda;
+  const int64_t M = c->mplane, D = (int64_t)c->g.q_max * c->seg;
+  double sc[2];
+  int rc;
+  // r = d - A m
+  if ((rc = born_of(c, c->m))) return finish(rc);
+  HIPCHECK(c, launch_sub(c->r, c->dobs, c->q, D, c->st));
+  // s = A^T r - lambda m, gamma = ||s||^2
+  if ((rc = adjoint_of(c, c->r))) return finish(rc);
+  HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, c->m, lam, M, c->partial,
+                               c->scal, c->st));
+  if ((rc = read_scalars(c, sc, 1))) return finish(rc);
+  double gamma = sc[0];
+  if (!std::isfinite(gamma))
+    return finish(fail(c, BRLS_ENONFINITE, "non-finite gradient norm"));
+  st.s0_norm = std::sqrt(gamma);
+  st.s_norm = st.s0_norm;
+  double ref = 0.0;
+  if (rtol > 0) {
+    if ((rc = adjoint_of(c, c->dobs))) return finish(rc);
+    HIPCHECK(c, launch_dot(c->gbuf, c->gbuf, M, c->partial, c->scal, c->st));
+    if ((rc = read_scalars(c, sc, 1))) return finish(rc);
+    ref = std::sqrt(sc[0]);
+  }
+  HIPCHECK(c, hipMemcpyAsync(c->p, c->s, M * 4, hipMemcpyDeviceToDevice,
+                             c->st));
+  for (int it = 0; it < max_iter; ++it) {
+    if (gamma == 0.0) break;
+    if (rtol > 0 && std::sqrt(gamma) <= rtol * ref) break;
+    if ((rc = born_of(c, c->p))) return finish(rc);
+    HIPCHECK(c, launch_dot(c->q, c->q, D, c->partial, c->scal, c->st));
+    HIPCHECK(c, launch_dot(c->p, c->p, M, c->partial, c->scal + 1, c->st));
+    if ((rc = read_scalars(c, sc, 2))) return finish(rc);
+    const double delta = sc[0] + lam * sc[1];
+    if (!std::isfinite(delta))
+      return finish(fail(c, BRLS_ENONFINITE, "non-finite CG scalar delta"));
+    if (!(delta > 0.0))
+      return finish(fail(c, BRLS_EBREAKDOWN, "CG breakdown: delta = %g",
+                         delta));
+    const double alpha = gamma / delta;
+    HIPCHECK(c, launch_axpy(c->m, c->p, alpha, M, c->st));
+    HIPCHECK(c, launch_axpy(c->r, c->q, -alpha, D, c->st));
+    if ((rc = adjoint_of(c, c->r))) return finish(rc);
+    HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, c->m, lam, M, c->partial,
+                                 c->scal, c->st));
+    if ((rc = read_scalars(c, sc, 1))) return finish(rc);
+    const double gnew = sc[0];
+    if (!std::isfinite(gnew))
+      return finish(fail(c, BRLS_ENONFINITE, "non-finite gradient norm"));
+    const double beta = gnew / gamma;
+    HIPCHECK(c, launch_xpby(c->p, c->s, beta, M, c->st));
+    gamma = gnew;
+    st.iters = it + 1;
+    st.s_norm = std::sqrt(gamma);
+  }
+  HIPCHECK(c, launch_dot(c->r, c->r, D, c->partial, c->scal, c->st));
+  if ((rc = read_scalars(c, sc, 1))) return finish(rc);
+  st.r_norm = std::sqrt(sc[0]);
+  return finish(BRLS_OK);
+}
+
+int brls_image(brls_ctx* c, float* out) {
+  if (!c || !out) return fail(c, BRLS_EINVAL, "NULL argument");
+  HIPCHECK(c, hipMemcpyAsync(out, c->m, c->mplane * 4, out_kind(c), c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_set_image(brls_ctx* c, const float* m) {
+  if (!c || !m) return fail(c, BRLS_EINVAL, "NULL argument");
+  HIPCHECK(c, hipMemcpyAsync(c->m, m, c->mplane * 4, in_kind(c), c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_apply_born(brls_ctx* c, const float* m, float* d_out) {
+  if (!c || !m || !d_out) return fail(c, BRLS_EINVAL, "NULL argument");
+  HIPCHECK(c, hipMemcpyAsync(c->born_in, m, c->mplane * 4, in_kind(c), c->st));
+  int rc = born_of(c, c->born_in);
+  if (rc) return rc;
+  int64_t off = 0;
+  for (int i : c->order) {
+    const Slot& sl = c->slots[i];
+    const int64_t nd = (int64_t)sl.nt * sl.nrec;
+    HIPCHECK(c, hipMemcpyAsync(d_out + off, c->q + sl.dat_off, nd * 4,
+                               out_kind(c), c->st));
+    off += nd;
+  }
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_apply_adjoint(brls_ctx* c, const float* d, float* m_out) {
+  if (!c || !d || !m_out) return fail(c, BRLS_EINVAL, "NULL argument");
+  HIPCHECK(c, launch_fill_f32(c->dscr, (int64_t)c->g.q_max * c->seg, 0.f,
+                              c->st));
+  int64_t off = 0;
+  for (int i : c->order) {
+    const Slot& sl = c->slots[i];
+    const int64_t nd = (int64_t)sl.nt * sl.nrec;
+    HIPCHECK(c, hipMemcpyAsync(c->dscr + sl.dat_off, d + off, nd * 4,
+                               in_kind(c), c->st));
+    off += nd;
+  }
+  int rc = adjoint_of(c, c->dscr);
+  if (rc) return rc;
+  if (c->order.empty())
+    HIPCHECK(c, launch_fill_f32(c->gbuf, c->mplane, 0.f, c->st));
+  HIPCHECK(c, hipMemcpyAsync(m_out, c->gbuf, c->mplane * 4, out_kind(c),
+                             c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_set_exec(brls_ctx* c, int32_t mode) {
+  if (!c) return BRLS_EINVAL;
+  if (mode < BRLS_EXEC_PLAIN || mode > BRLS_EXEC_GRAPH)
+    return fail(c, BRLS_EINVAL, "unknown exec mode %d", mode);
+  c->exec = mode;
+  return BRLS_OK;
+}
+
+int brls_tile_count(int32_t* n) {
+  if (!n) return BRLS_EINVAL;
+  *n = tile_shape_count();
+  return BRLS_OK;
+}
+
+int brls_tile_info(int32_t v, int32_t* tx, int32_t* tz, int32_t* pb) {
+  if (v < 0 || v >= tile_shape_count()) return BRLS_EINVAL;
+  const TileShape s = tile_shape(v);
+  if (tx) *tx = s.tx;
+  if (tz) *tz = s.tz;
+  if (pb) *pb = s.ntz;
+  return BRLS_OK;
+}
+
+static int set_tile_impl(brls_ctx* c, int v, int per_block) {
+  if (v < 0 || v >= tile_shape_count())
+    return fail(c, BRLS_EINVAL, "tile variant %d out of range", v);
+  if (per_block < 1) per_block = 1;
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  const bool changed = v != c->variant;
+  set_variant_geo(c, v);
+  c->per_block = per_block;
+  if (changed) {
+    drop_graphs(c);
+    for (auto& sl : c->slots)
+      if (sl.used) {
+        int rc = build_receiver_tiles(c, sl);
+        if (rc) return rc;
+      }
+  }
+  return BRLS_OK;
+}
+
+int brls_set_tile(brls_ctx* c, int32_t variant) {
+  if (!c) return BRLS_EINVAL;
+  return set_tile_impl(c, variant < 0 ? 0 : variant, c->per_block);
+}
+
+int brls_set_shots_per_block(brls_ctx* c, int32_t per_block) {
+  if (!c || per_block < 1)
+    return fail(c, BRLS_EINVAL, "shots per block must be >= 1");
+  c->per_block = per_block;
+  return BRLS_OK;
+}
+
+int brls_autotune(brls_ctx* c, int32_t* best) {
+  if (!c) return BRLS_EINVAL;
+  int rc;
+  if ((rc = ensure_tab(c)) || (rc = ensure_backgrounds(c)) ||
+      (rc = ensure_tab(c)))
+    return rc;
+  const int nsh = (int)c->order.size();
+  if (nsh == 0) {
+    if (best) *best = c->variant;
+    return BRLS_OK;
+  }
+  const int saved_exec = c->exec;
+  c->exec = BRLS_EXEC_BATCHED;
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0));
+  HIPCHECK(c, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int best_v = c->variant, best_pb = c->per_block;
+  for (int v = 0; v < tile_shape_count(); ++v) {
+    for (int pb = 1; pb <= 8; pb *= 2) {
+      if (pb > nsh && pb > 1) break;
+      if ((rc = set_tile_impl(c, v, pb))) return rc;
+      HIPCHECK(c, hipEventRecord(e0, c->st));
+      if ((rc = enqueue_born(c, 1)) || (rc = enqueue_adjoint(c, 1))) return rc;
+      HIPCHECK(c, hipEventRecord(e1, c->st));
+      HIPCHECK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_v = v;
+        best_pb = pb;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->exec = saved_exec;
+  if ((rc = set_tile_impl(c, best_v, best_pb))) return rc;
+  if (best) *best = best_v;
+  return BRLS_OK;
+}
+
+int brls_get_tile(const brls_ctx* c, int32_t* variant, int32_t* per_block) {
+  if (!c) return BRLS_EINVAL;
+  if (variant) *variant = c->variant;
+  if (per_block) *per_block = c->per_block;
+  return BRLS_OK;
+}
+
+int brls_kernel_timing(brls_ctx* c, int32_t enable) {
+  if (!c) return BRLS_EINVAL;
+  c->timing = enable != 0;
+  return BRLS_OK;
+}
+
+int brls_kernel_stats(brls_ctx* c, brls_kstat* out, int32_t cap, int32_t* n) {
+  if (!c || !n) return BRLS_EINVAL;
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  int64_t cnt[kTNumKinds] = {0};
+  double tot[kTNumKinds] = {0};
+  for (auto& t : c->timers) {
+    float ms = 0.f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, t.a, t.b));
+    cnt[t.kind]++;
+    tot[t.kind] += ms;
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  c->timers.clear();
+  int k = 0;
+  for (int i = 0; i < kTNumKinds; ++i) {
+    if (!cnt[i]) continue;
+    if (out && k < cap) {
+      std::snprintf(out[k].name, sizeof out[k].name, "%s", kTimerNames[i]);
+      out[k].launches = cnt[i];
+      out[k].total_ms = tot[i];
+    }
+    ++k;
+  }
+  *n = k;
+  return BRLS_OK;
+}
+
+int brls_memory_bytes(const brls_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return BRLS_EINVAL;
+  *bytes = c->mem_bytes;
+  return BRLS_OK;
+}
+
+int brls_sync(brls_ctx* c) {
+  if (!c) return BRLS_EINVAL;
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+}  // extern "C"

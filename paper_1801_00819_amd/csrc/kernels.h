@@ -1,0 +1,51 @@
+// Host-side launchers of the library's kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.h"
+
+namespace brls {
+
+struct TileShape {
+  int tx, tz, ntz;  // tile width (x), tile height (z), thread rows
+};
+
+int tile_shape_count();
+TileShape tile_shape(int variant);
+
+// One time step for all shots of `a` (mode: StepMode).
+hipError_t launch_step2d(int variant, int mode, const StepArgs& a,
+                         hipStream_t st);
+hipError_t launch_born_last(const ShotDev* tab, int nshots, int nrec_max,
+                            float* dat, hipStream_t st);
+hipError_t launch_adj_finalize(const double* acc, int ngroups,
+                               const Geo2D& g, const float* wp, float* out,
+                               hipStream_t st);
+
+// Vector kernels (blas.hip). Sums are accumulated in float64 in a fixed
+// order (per-block partials, then one block), so results are deterministic.
+constexpr int kDotBlocks = 1024;
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+// partial[0..kDotBlocks) of sum(a*b); then out[0] = sum(partial)
+hipError_t launch_dot(const float* a, const float* b, int64_t n,
+                      double* partial, double* out, hipStream_t st);
+// y += alpha * x (alpha applied in float64)
+hipError_t launch_axpy(float* y, const float* x, double alpha, int64_t n,
+                       hipStream_t st);
+// p = s + beta * p
+hipError_t launch_xpby(float* p, const float* s, double beta, int64_t n,
+                       hipStream_t st);
+// r = d - q
+hipError_t launch_sub(float* r, const float* d, const float* q, int64_t n,
+                      hipStream_t st);
+// s = g - lambda * m, and out[0] = ||s||^2 (float64)
+hipError_t launch_grad_norm(float* s, const float* g, const float* m,
+                            double lambda, int64_t n, double* partial,
+                            double* out, hipStream_t st);
+// flag[0] = 1 if any entry of x is NaN or Inf (flag must start at 0)
+hipError_t launch_nonfinite(const float* x, int64_t n, int* flag,
+                            hipStream_t st);
+
+}  // namespace brls

@@ -1,0 +1,82 @@
+// Device-side data layout shared by the stencil kernels and the host engine.
+//
+// Wavefields live on the padded grid (model + nb absorbing cells per face)
+// stored with a 4-cell ring of zeros around it, so the radius-4 stencil never
+// needs a bounds test: padded point (z, x) sits at
+//     (z + 4) * pitch + x + xoff
+// where xoff puts the first model column (x = nb) on a 128-byte boundary and
+// pitch is a multiple of 32 floats. The ring (and everything outside the
+// padded grid) is never written, so it stays zero: the stencil sees u = 0
+// outside the padded grid.
+//
+// Each field is advanced in "difference form": besides u^n the kernels keep
+// v^n = u^n - u^{n-1}. The leapfrog update of a damped wave equation
+//     u^{n+1} = C1 (2u^n + W L u^n + s^n) - C2 u^{n-1}
+// is, exactly, v^{n+1} = C2 v^n + C1 (W L u^n + s^n), u^{n+1} = u^n + v^{n+1}.
+// Carrying v instead of u^{n-1}, and evaluating L on differences
+// (u[i+k] - u[i]), keeps float32 rounding from being amplified by the small
+// (omega dt)^2 of well-sampled waves.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace brls {
+
+constexpr int kRadius = 4;
+constexpr int kGhost = 4;  // zero ring around the padded grid
+
+// 8th-order central second-derivative weights for offsets 1..4 (the centre
+// weight is implied: the difference form needs only these).
+struct StencilW {
+  float c1, c2, c3, c4;
+};
+
+// Per-shot state of a window slot, read by the kernels through a device
+// table in window order.
+struct ShotDev {
+  float* u0;        // displacement, even time levels (storage layout)
+  float* u1;        // displacement, odd time levels
+  float* v;         // difference field, updated in place
+  float* d2;        // Born source cache: [nt-1][nz][nx] (model region)
+  const int* rptr;  // receivers per tile: CSR offsets [ntiles + 1]
+  const int2* rent; // (local index lz*TX + lx, receiver index)
+  const int* rsidx; // storage index of each receiver
+  const float* wav; // h^2 * source wavelet [nt]
+  int64_t dat_off;  // offset of this shot's [nt][nrec] segment in data vectors
+  int nt;
+  int nrec;
+  int src_z, src_x; // padded grid position of the source
+};
+
+struct Geo2D {
+  int pz, px;        // padded grid
+  int nz, nx, nb;    // model grid, sponge width
+  int pitch;         // storage row pitch (floats)
+  int xoff;          // storage column of padded x = 0
+  int x_org;         // padded x of the first tile column (<= 0)
+  int ntx, ntz, ntiles;
+  float eta_scale;   // eta_max * dt / 2 / nb^2
+  StencilW w;
+};
+
+enum StepMode { kBackground = 0, kBorn = 1, kAdjoint = 2 };
+
+struct StepArgs {
+  Geo2D g;
+  const ShotDev* tab;  // shots of this launch
+  int nshots;          // shots in tab
+  int per_block;       // shots handled by one block (sequentially)
+  int ngroups;         // ceil(nshots / per_block)
+  int n;               // time level: input level (background, Born) or
+                       // output level k (adjoint)
+  const float* wp;     // W' = v^2 dt^2 / h^2, storage layout
+  const float* pm;     // Born: model perturbation [nz][nx]
+  float* dat;          // Born: output data base; adjoint: input residual base
+  double* acc;         // adjoint: image accumulators [ngroups][nz][nx]
+};
+
+__host__ __device__ inline int64_t sidx2(const Geo2D& g, int z, int x) {
+  return (int64_t)(z + kGhost) * g.pitch + x + g.xoff;
+}
+
+}  // namespace brls

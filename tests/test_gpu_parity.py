@@ -1,0 +1,318 @@
+"""GPU library vs the FP64 oracle, through the C ABI.
+
+Bars: relative L2 <= 1e-5 per application of A or A^T; <= 1e-4 on final
+images of a window chain. Inputs are seeded and rounded to float32 before
+either side sees them.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import (add_shot, f32, open_ctx, oracle_problem, ragged2d,
+                         rel, split)
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 1e-5
+IMG_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1801_00819_amd as P
+    return P
+
+
+def _case(name):
+    if name == "config0":
+        w = synth.config0()
+        return w, [0, 1]
+    w = ragged2d()
+    return w, [0, 1, 2]
+
+
+@pytest.mark.parametrize("name", ["config0", "ragged2d"])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_born_matches_oracle(P, name, mode):
+    w, idx = _case(name)
+    print(f"born parity {name} mode={mode}", flush=True)
+    ctx = open_ctx(w, q_max=len(idx))
+    ctx.set_exec(mode)
+    for i in idx:
+        add_shot(ctx, w, i)
+    prob = oracle_problem(w)
+    for m in (w.m_true, synth.gaussian(w.model_shape, 31) * 0.05):
+        m32 = f32(m)
+        got = split(w, idx, ctx.apply_born(m32))
+        want = prob.born(m32.astype(np.float64), idx)
+        for g_, w_ in zip(got, want):
+            assert rel(g_, w_) <= OP_TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["config0", "ragged2d"])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_adjoint_matches_oracle(P, name, mode):
+    w, idx = _case(name)
+    print(f"adjoint parity {name} mode={mode}", flush=True)
+    ctx = open_ctx(w, q_max=len(idx))
+    ctx.set_exec(mode)
+    for i in idx:
+        add_shot(ctx, w, i)
+    prob = oracle_problem(w)
+    r = [f32(synth.gaussian((w.shots[i].nt, w.shots[i].nrec), 40 + i))
+         for i in idx]
+    got = ctx.apply_adjoint(np.concatenate([x.ravel() for x in r]))
+    want = prob.adjoint([x.astype(np.float64) for x in r], idx)
+    assert rel(got, want) <= OP_TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("variant", range(6))
+def test_every_tile_shape_matches_oracle(P, variant):
+    w, idx = _case("ragged2d")
+    print(f"tile variant {variant}", flush=True)
+    ctx = open_ctx(w, q_max=3)
+    for pb in (1, 2, 3):
+        ctx.set_tile(variant, pb)
+        for i in idx:
+            if pb == 1:
+                add_shot(ctx, w, i)
+        prob = oracle_problem(w)
+        m32 = f32(w.m_true)
+        got = split(w, idx, ctx.apply_born(m32))
+        want = prob.born(m32.astype(np.float64), idx)
+        for g_, w_ in zip(got, want):
+            assert rel(g_, w_) <= OP_TOL
+        r = np.concatenate([x.ravel() for x in got])
+        g = ctx.apply_adjoint(r)
+        wg = prob.adjoint([x.astype(np.float64) for x in got], idx)
+        assert rel(g, wg) <= OP_TOL
+    ctx.close()
+
+
+def test_gpu_dot_product_identity(P):
+    w, idx = _case("ragged2d")
+    ctx = open_ctx(w, q_max=3)
+    for i in idx:
+        add_shot(ctx, w, i)
+    m = f32(synth.gaussian(w.model_shape, 5))
+    d = f32(synth.gaussian(ctx.window_data_size(), 6))
+    lhs = float(np.dot(ctx.apply_born(m).astype(np.float64),
+                       d.astype(np.float64)))
+    rhs = float(np.dot(m.ravel().astype(np.float64),
+                       ctx.apply_adjoint(d).ravel().astype(np.float64)))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    ctx.close()
+
+
+def test_device_pointers_match_host(P):
+    import torch
+    w, idx = _case("config0")
+    hctx = open_ctx(w, q_max=2)
+    dctx = open_ctx(w, q_max=2, device=True)
+    for i in idx:
+        add_shot(hctx, w, i)
+        s = w.shots[i]
+        dctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+    m = f32(w.m_true)
+    dh = hctx.apply_born(m)
+    dd = dctx.apply_born(torch.from_numpy(m).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(dh, dd.cpu().numpy())
+    gd = dctx.apply_adjoint(dd)
+    gh = hctx.apply_adjoint(dh)
+    torch.cuda.synchronize()
+    assert np.array_equal(gh, gd.cpu().numpy())
+    hctx.close()
+    dctx.close()
+
+
+def test_runs_are_bitwise_repeatable(P):
+    w, idx = _case("ragged2d")
+    ctx = open_ctx(w, q_max=3)
+    for i in idx:
+        add_shot(ctx, w, i)
+    m = f32(w.m_true)
+    a = ctx.apply_born(m)
+    b = ctx.apply_born(m)
+    assert np.array_equal(a, b)
+    ga = ctx.apply_adjoint(a)
+    gb = ctx.apply_adjoint(a)
+    assert np.array_equal(ga, gb)
+    ctx.close()
+
+
+def _chain_inputs(w, noise_seed_cfg):
+    prob = oracle_problem(w)
+    noise = [synth.gaussian((s.nt, s.nrec), 1000 * noise_seed_cfg + 1 + k)
+             for k, s in enumerate(w.shots)]
+    import oracle
+    data = [f32(d) for d in oracle.synthesize_data(
+        prob, f32(w.m_true).astype(np.float64), w.noise_rel, noise)]
+    lam = w.lam_rel * oracle.power_norm(prob, w.windows()[0], 20, seed=3)
+    return prob, data, lam
+
+
+def _gpu_chain(ctx, w, data, niter):
+    held = []
+    for win in w.windows():
+        for i in list(held):
+            if i not in win:
+                ctx.downdate(i)
+                held.remove(i)
+        for i in win:
+            if i not in held:
+                add_shot(ctx, w, i, data[i])
+                held.append(i)
+        st = ctx.solve_window(niter)
+        assert st["iters"] == niter
+    return ctx.image()
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_window_chain_matches_oracle_config0(P, mode):
+    """Full block-row chain of the 64 x 64 workload: 3 windows of 2 shots
+    sliding by 1, 10 CG iterations each, warm-started."""
+    import oracle
+    w = synth.config0()
+    prob, data, lam = _chain_inputs(w, 0)
+    ref = oracle.chain(prob, [d.astype(np.float64) for d in data],
+                       w.windows(), lam, w.niter)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    ctx.set_exec(mode)
+    img = _gpu_chain(ctx, w, data, w.niter)
+    assert rel(img, ref.m) <= IMG_TOL
+    ctx.close()
+
+
+def test_window_solve_matches_oracle_iterate_norms(P):
+    import oracle
+    w = synth.config0()
+    prob, data, lam = _chain_inputs(w, 0)
+    idx = w.windows()[0]
+    res = oracle.cgls(prob, idx, [data[i].astype(np.float64) for i in idx],
+                      lam, 5)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    for i in idx:
+        add_shot(ctx, w, i, data[i])
+    st = ctx.solve_window(5)
+    assert abs(st["s0_norm"] - res.s0_norm) <= 1e-5 * res.s0_norm
+    assert abs(st["s_norm"] - res.s_norms[-1]) <= 1e-3 * res.s_norms[-1]
+    assert abs(st["r_norm"] - res.r_norms[-1]) <= 1e-5 * res.r_norms[-1]
+    assert rel(ctx.image(), res.m) <= IMG_TOL
+    ctx.close()
+
+
+def test_rtol_stop_and_warm_start_match_oracle(P):
+    """Residual-based stop (||s|| <= rtol ||A^T d||) and eq. 11's warm
+    start: iteration counts agree with the oracle's (to one iteration, the
+    threshold being crossed in rounding) and starting window 1 from window
+    0's image never needs more iterations than starting from zero."""
+    import oracle
+    w = synth.config0()
+    prob, data, lam = _chain_inputs(w, 0)
+    d64 = [d.astype(np.float64) for d in data]
+    rt = 1e-3
+    r0 = oracle.cgls(prob, [0, 1], d64[:2], lam, 200, rtol=rt)
+    cold_o = oracle.cgls(prob, [1, 2], d64[1:3], lam, 200, rtol=rt)
+    warm_o = oracle.cgls(prob, [1, 2], d64[1:3], lam, 200, m0=r0.m, rtol=rt)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    for i in (0, 1):
+        add_shot(ctx, w, i, data[i])
+    st0 = ctx.solve_window(200, rtol=rt)
+    assert abs(st0["iters"] - r0.iters) <= 1
+    img0 = ctx.image()
+    ctx.downdate(0)
+    add_shot(ctx, w, 2, data[2])
+    warm = ctx.solve_window(200, rtol=rt)
+    ctx.set_image(np.zeros(w.model_shape, np.float32))
+    cold = ctx.solve_window(200, rtol=rt)
+    assert abs(warm["iters"] - warm_o.iters) <= 1
+    assert abs(cold["iters"] - cold_o.iters) <= 1
+    assert warm["iters"] <= cold["iters"]
+    assert warm_o.iters <= cold_o.iters
+    assert rel(img0, r0.m) <= IMG_TOL
+    ctx.close()
+
+
+def test_error_paths(P):
+    from paper_1801_00819_amd import BrlsError, _lib as L
+    w = synth.config0()
+    ctx = open_ctx(w, q_max=1)
+    st = ctx.solve_window(5)  # empty window
+    assert st["iters"] == 0
+    add_shot(ctx, w, 0)
+    with pytest.raises(BrlsError) as e:
+        add_shot(ctx, w, 1)
+    assert e.value.code == L.BRLS_EFULL
+    with pytest.raises(BrlsError) as e:
+        add_shot(ctx, w, 0)
+    assert e.value.code == L.BRLS_EDUP
+    with pytest.raises(BrlsError) as e:
+        ctx.downdate(77)
+    assert e.value.code == L.BRLS_ENOSHOT
+    ctx.downdate(0)
+    bad = np.zeros((w.shots[1].nt, w.shots[1].nrec), np.float32)
+    bad[3, 4] = np.nan
+    with pytest.raises(BrlsError) as e:
+        add_shot(ctx, w, 1, bad)
+    assert e.value.code == L.BRLS_ENONFINITE
+    s = w.shots[1]
+    with pytest.raises(BrlsError) as e:
+        ctx.update(5, (64, 0, 3), s.rec, s.nt, s.f0)
+    assert e.value.code == L.BRLS_EINVAL
+    # zero data, zero image: zero gradient, nothing to do
+    add_shot(ctx, w, 1)
+    assert ctx.solve_window(4)["iters"] == 0
+    ctx.close()
+    import paper_1801_00819_amd as P_
+    fast = synth.config0()
+    fast.vel[:] = 6000.0  # v dt / h = 0.6 > 0.5546
+    with pytest.raises(BrlsError) as e:
+        open_ctx(fast)
+    assert e.value.code == L.BRLS_EINVAL
+    assert P_ is not None
+
+
+# ---------------------------------------------------------------------------
+# Full-size workload: 512 x 1024, nt = 3000, an 8-shot window (the launch
+# configuration the benchmark times). The oracle computes single shots.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def big():
+    w = synth.config1()
+    idx = list(range(8))
+    return w, idx
+
+
+def test_full_size_born_shot_matches_oracle(P, big):
+    w, idx = big
+    print("config1 born, 8-shot window, graph mode", flush=True)
+    ctx = open_ctx(w, q_max=8)
+    for i in idx:
+        add_shot(ctx, w, i)
+    m32 = f32(w.m_true)
+    got = split(w, idx, ctx.apply_born(m32))
+    ctx.close()
+    prob = oracle_problem(w, shots=[w.shots[0]])
+    want = prob.born_shot(0, m32.astype(np.float64))
+    assert rel(got[0], want) <= OP_TOL
+
+
+def test_full_size_adjoint_shot_matches_oracle(P, big):
+    w, idx = big
+    print("config1 adjoint, 8-shot window, graph mode", flush=True)
+    ctx = open_ctx(w, q_max=8)
+    for i in idx:
+        add_shot(ctx, w, i)
+    s = w.shots[7]
+    r7 = f32(synth.gaussian((s.nt, s.nrec), 77))
+    parts = [np.zeros(w.shots[i].nt * w.shots[i].nrec, np.float32)
+             for i in idx]
+    parts[7] = r7.ravel()
+    got = ctx.apply_adjoint(np.concatenate(parts))
+    ctx.close()
+    prob = oracle_problem(w, shots=[s])
+    want = prob.adjoint_shot(0, r7.astype(np.float64))
+    assert rel(got, want) <= OP_TOL
