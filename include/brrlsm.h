@@ -75,6 +75,12 @@ typedef struct {
   double h;           /* grid spacing (m) */
   double dt;          /* time step (s) */
   double lambda;      /* damping of eq. 3, absolute */
+  int32_t ckpt_interval; /* background wavefield strategy:
+                            0  store its Born source for every step (fast;
+                               (nt_max-1)*nz*nx floats per shot);
+                            k > 0  keep the background state every k steps
+                               and recompute it (2 fields per checkpoint);
+                            -1 checkpoints every ceil(sqrt(nt_max)) steps */
   uint32_t flags;     /* BRLS_DEVICE_PTRS */
 } brls_grid;
 
@@ -170,17 +176,25 @@ int brls_set_exec(brls_ctx* ctx, int32_t mode);
 
 /* Tile shape of the stencil kernels: index into the compiled variants
  * (brls_tile_count); -1 restores the default. brls_tile_info reports a
- * variant's tile width tx, height tz and thread rows. */
+ * variant's tile width tx, height tz, thread rows, and whether a block
+ * issues the next shot's loads before computing the current one. */
 int brls_set_tile(brls_ctx* ctx, int32_t variant);
 int brls_tile_count(int32_t* n);
 int brls_tile_info(int32_t variant, int32_t* tx, int32_t* tz,
-                   int32_t* thread_rows);
+                   int32_t* thread_rows, int32_t* pipelined);
 
 /* Shots one block handles in turn in batched modes (default 4). */
 int brls_set_shots_per_block(brls_ctx* ctx, int32_t per_block);
 int brls_get_tile(const brls_ctx* ctx, int32_t* variant, int32_t* per_block);
 
-/* Time every tile variant and shots-per-block choice on the current window
+/* Grid shape of the stencil kernels: 0 (default) launches one block per
+ * (tile, shot group) work item; 1 launches only as many blocks as fit on the
+ * device at once, each looping over work items. */
+int brls_set_resident_grid(brls_ctx* ctx, int32_t enable);
+int brls_get_resident_grid(const brls_ctx* ctx, int32_t* enable);
+
+/* Time every tile variant, shots-per-block choice and grid shape on the
+ * current window
  * (one Born and one adjoint application each, results discarded) and keep
  * the fastest. Returns the chosen variant in *best. */
 int brls_autotune(brls_ctx* ctx, int32_t* best);

@@ -196,6 +196,18 @@ class Context:
 
     get_tile = brls_get_tile
 
+    def brls_set_resident_grid(self, enable: bool):
+        self._check(L.lib().brls_set_resident_grid(self._h, int(bool(enable))))
+
+    set_resident_grid = brls_set_resident_grid
+
+    def brls_get_resident_grid(self) -> bool:
+        v = ctypes.c_int32()
+        self._check(L.lib().brls_get_resident_grid(self._h, ctypes.byref(v)))
+        return bool(v.value)
+
+    get_resident_grid = brls_get_resident_grid
+
     def brls_autotune(self) -> int:
         best = ctypes.c_int32()
         self._check(L.lib().brls_autotune(self._h, ctypes.byref(best)))
@@ -233,15 +245,19 @@ class Context:
 
 def brls_open(ndim: int, nz: int, ny: int, nx: int, nb: int, nt_max: int,
               nrec_max: int, q_max: int, h: float, dt: float, lam: float,
-              vel: np.ndarray, device: bool = False, stream=None) -> Context:
+              vel: np.ndarray, device: bool = False, stream=None,
+              ckpt_interval: int = 0) -> Context:
     """Open a context (velocity ``vel`` [nz][ny][nx], m/s, host array).
 
     ``stream``: a hipStream_t as int; with ``device=True`` and no stream given,
-    torch's current stream is used."""
+    torch's current stream is used. ``ckpt_interval``: 0 stores the Born
+    source of every step, k > 0 checkpoints the background every k steps and
+    recomputes it, -1 picks k = ceil(sqrt(nt_max))."""
     g = L.brls_grid()
     g.ndim, g.nz, g.ny, g.nx, g.nb = ndim, nz, ny, nx, nb
     g.nt_max, g.nrec_max, g.q_max = nt_max, nrec_max, q_max
     g.h, g.dt, g.lambda_ = float(h), float(dt), float(lam)
+    g.ckpt_interval = int(ckpt_interval)
     g.flags = L.BRLS_DEVICE_PTRS if device else 0
     if device and stream is None:
         import torch
@@ -260,8 +276,8 @@ def tile_variants():
     L.check(L.lib().brls_tile_count(ctypes.byref(n)))
     out = []
     for v in range(n.value):
-        tx, tz, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        tx, tz, r, pp = (ctypes.c_int32() for _ in range(4))
         L.check(L.lib().brls_tile_info(v, ctypes.byref(tx), ctypes.byref(tz),
-                                       ctypes.byref(r)))
-        out.append((tx.value, tz.value, r.value))
+                                       ctypes.byref(r), ctypes.byref(pp)))
+        out.append((tx.value, tz.value, r.value, pp.value))
     return out

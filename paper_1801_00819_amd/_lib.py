@@ -41,7 +41,8 @@ class brls_grid(ctypes.Structure):
                 ("nb", ctypes.c_int32), ("nt_max", ctypes.c_int32),
                 ("nrec_max", ctypes.c_int32), ("q_max", ctypes.c_int32),
                 ("h", ctypes.c_double), ("dt", ctypes.c_double),
-                ("lambda_", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("lambda_", ctypes.c_double),
+                ("ckpt_interval", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class brls_shot(ctypes.Structure):
@@ -89,10 +90,13 @@ SIGNATURES = [
     ("brls_set_tile", _I32, [_VP, _I32]),
     ("brls_tile_count", _I32, [ctypes.POINTER(_I32)]),
     ("brls_tile_info", _I32, [_I32, ctypes.POINTER(_I32),
-                              ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+                              ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                              ctypes.POINTER(_I32)]),
     ("brls_set_shots_per_block", _I32, [_VP, _I32]),
     ("brls_get_tile", _I32, [_VP, ctypes.POINTER(_I32),
                              ctypes.POINTER(_I32)]),
+    ("brls_set_resident_grid", _I32, [_VP, _I32]),
+    ("brls_get_resident_grid", _I32, [_VP, ctypes.POINTER(_I32)]),
     ("brls_autotune", _I32, [_VP, ctypes.POINTER(_I32)]),
     ("brls_kernel_timing", _I32, [_VP, _I32]),
     ("brls_kernel_stats", _I32, [_VP, ctypes.POINTER(brls_kstat), _I32,

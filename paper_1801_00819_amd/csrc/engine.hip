@@ -50,7 +50,10 @@ struct Slot {
   std::vector<int32_t> rec;  // host copy (z, y, x)
   bool bg_ready = false;
   float* fields = nullptr;   // u0 | u1 | v
-  float* d2 = nullptr;       // [nt_max-1][nz][nx]
+  float* bgf = nullptr;      // background u0 | u1 | v (checkpoint mode)
+  float* d2 = nullptr;       // [nt_max-1][nz][nx] (cache mode)
+  float* ck = nullptr;       // [nseg][u | v][field] (checkpoint mode)
+  float* segd2 = nullptr;    // [ckpt_k][nz][nx] (checkpoint mode)
   float* wav = nullptr;      // [nt_max]
   int* rptr = nullptr;       // [ntiles_max + 1]
   int2* rent = nullptr;      // [nrec_max]
@@ -69,7 +72,8 @@ const char* kTimerNames[kTNumKinds] = {"background_step", "born_step",
                                        "adjoint_step", "born_graph",
                                        "adjoint_graph"};
 
-using GraphKey = std::tuple<int, int, int, int, int>;  // op, nshots, pb, var, nt
+// op, shots, shots per block, tile variant, time steps, resident grid
+using GraphKey = std::tuple<int, int, int, int, int, int>;
 
 }  // namespace
 
@@ -81,12 +85,15 @@ struct brls_ctx {
   Geo2D geo{};
   int variant = 0;
   int per_block = 4;
+  int resident_grid = 0;
   int exec = BRLS_EXEC_GRAPH;
   int rows_alloc = 0;
   int64_t fs = 0;      // floats per field buffer
   int64_t mplane = 0;  // model points
   int64_t seg = 0;     // floats per shot segment of data vectors
   int ntiles_max = 0;
+  int ckpt_k = 0;       // 0: cache every Born-source frame; else interval
+  int nseg_max = 0;     // checkpoints per shot
   float* wp = nullptr;
   float* fields_all = nullptr;
   float *m = nullptr, *p = nullptr, *s = nullptr, *gbuf = nullptr,
@@ -199,10 +206,12 @@ int build_receiver_tiles(brls_ctx* c, Slot& sl) {
 
 ShotDev shot_dev(const brls_ctx* c, const Slot& sl) {
   ShotDev d{};
-  d.u0 = sl.fields;
-  d.u1 = sl.fields + c->fs;
-  d.v = sl.fields + 2 * c->fs;
-  d.d2 = sl.d2;
+  for (int k = 0; k < 3; ++k) {
+    d.f[k] = sl.fields + k * c->fs;
+    d.b[k] = (c->ckpt_k ? sl.bgf : sl.fields) + k * c->fs;
+  }
+  d.d2 = c->ckpt_k ? sl.segd2 : sl.d2;
+  d.ck = sl.ck;
   d.rptr = sl.rptr;
   d.rent = sl.rent;
   d.rsidx = sl.rsidx;
@@ -263,13 +272,17 @@ StepArgs base_args(const brls_ctx* c) {
   StepArgs a{};
   a.g = c->geo;
   a.wp = c->wp;
+  a.resident_grid = c->resident_grid;
   return a;
 }
 
 // One time step over `nshots` table entries starting at `tab`.
 int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
-         int per_block, const float* pm, float* dat, double* acc) {
+         int per_block, const float* pm, float* dat, double* acc,
+         int d2_n0 = 0, int write_d2 = 0) {
   StepArgs a = base_args(c);
+  a.d2_n0 = d2_n0;
+  a.write_d2 = write_d2;
   a.tab = tab;
   a.nshots = nshots;
   a.per_block = per_block;
@@ -280,18 +293,25 @@ int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
   a.acc = acc;
   Timer t;
   int rc = timed_begin(c, mode == kBackground ? kTBackground
-                          : mode == kBorn     ? kTBorn
-                                              : kTAdjoint,
+                          : mode == kAdjoint  ? kTAdjoint
+                                              : kTBorn,
                        &t);
   if (rc) return rc;
   HIPCHECK(c, launch_step2d(c->variant, mode, a, c->st));
   return timed_end(c, &t);
 }
 
+int64_t field_floats(const brls_ctx* c) {
+  return (int64_t)c->g.q_max * (c->ckpt_k ? 6 : 3) * c->fs;
+}
+
 int zero_fields(brls_ctx* c) {
-  HIPCHECK(c, launch_fill_f32(c->fields_all,
-                              (int64_t)c->g.q_max * 3 * c->fs, 0.f, c->st));
+  HIPCHECK(c, launch_fill_f32(c->fields_all, field_floats(c), 0.f, c->st));
   return BRLS_OK;
+}
+
+int nseg_of(const brls_ctx* c, int nt) {
+  return (nt - 1 + c->ckpt_k - 1) / c->ckpt_k;
 }
 
 // Background wavefields (and Born-source caches) of shots that lack them.
@@ -308,20 +328,32 @@ int ensure_backgrounds(brls_ctx* c) {
   int rc;
   for (int i : todo) {
     Slot& sl = c->slots[i];
-    HIPCHECK(c, launch_fill_f32(sl.fields, 3 * c->fs, 0.f, c->st));
+    HIPCHECK(c, launch_fill_f32(c->ckpt_k ? sl.bgf : sl.fields, 3 * c->fs,
+                                0.f, c->st));
   }
   const int ntm = nt_max_of(c, todo);
   const int nsh = (int)todo.size();
+  // cache mode: every Born-source frame stored; checkpoint mode: the state
+  // every ckpt_k steps
+  const int wr = c->ckpt_k ? 0 : 1;
+  auto save = [&](const ShotDev* tab, int ns, int n) -> int {
+    if (!c->ckpt_k || n % c->ckpt_k) return BRLS_OK;
+    HIPCHECK(c, launch_ckpt(tab, ns, n, n / c->ckpt_k, c->fs, 0, c->st));
+    return BRLS_OK;
+  };
   if (c->exec == BRLS_EXEC_PLAIN) {
     for (int k = 0; k < nsh; ++k)
       for (int n = 0; n + 1 < c->slots[todo[k]].nt; ++n)
-        if ((rc = step(c, kBackground, n, c->bgtab_dev + k, 1, 1, nullptr,
-                       nullptr, nullptr)))
+        if ((rc = save(c->bgtab_dev + k, 1, n)) ||
+            (rc = step(c, kBackground, n, c->bgtab_dev + k, 1, 1, nullptr,
+                       nullptr, nullptr, 0, wr)))
           return rc;
   } else {
     for (int n = 0; n + 1 < ntm; ++n)
-      if ((rc = step(c, kBackground, n, c->bgtab_dev, nsh,
-                     std::min(c->per_block, nsh), nullptr, nullptr, nullptr)))
+      if ((rc = save(c->bgtab_dev, nsh, n)) ||
+          (rc = step(c, kBackground, n, c->bgtab_dev, nsh,
+                     std::min(c->per_block, nsh), nullptr, nullptr, nullptr,
+                     0, wr)))
         return rc;
   }
   HIPCHECK(c, hipStreamSynchronize(c->st));
@@ -330,25 +362,60 @@ int ensure_backgrounds(brls_ctx* c) {
 }
 
 // Kernel sequence of one operator application (also what a graph captures).
+// Cache mode reads the stored Born-source frames; checkpoint mode advances
+// the background alongside (Born) or recomputes it segment by segment from
+// its checkpoints (adjoint).
 int enqueue_born(brls_ctx* c, int batched) {
   const int nsh = (int)c->order.size();
   const int ntm = nt_max_of(c, c->order);
+  const int mode = c->ckpt_k ? kBornFused : kBorn;
   int rc;
   if ((rc = zero_fields(c))) return rc;
   if (!batched) {
     for (int k = 0; k < nsh; ++k)
       for (int n = 0; n + 1 < c->slots[c->order[k]].nt; ++n)
-        if ((rc = step(c, kBorn, n, c->tab_dev + k, 1, 1, c->born_in, c->q,
+        if ((rc = step(c, mode, n, c->tab_dev + k, 1, 1, c->born_in, c->q,
                        nullptr)))
           return rc;
   } else {
     const int pb = std::min(c->per_block, nsh);
     for (int n = 0; n + 1 < ntm; ++n)
-      if ((rc = step(c, kBorn, n, c->tab_dev, nsh, pb, c->born_in, c->q,
+      if ((rc = step(c, mode, n, c->tab_dev, nsh, pb, c->born_in, c->q,
                      nullptr)))
         return rc;
   }
   HIPCHECK(c, launch_born_last(c->tab_dev, nsh, c->g.nrec_max, c->q, c->st));
+  return BRLS_OK;
+}
+
+// Adjoint steps k = k_hi .. k_lo (descending) of the shots in tab, the
+// Born-source frames of levels >= d2_n0 being available.
+int adjoint_steps(brls_ctx* c, const ShotDev* tab, int nsh, int pb, int k_hi,
+                  int k_lo, int d2_n0) {
+  int rc;
+  for (int k = k_hi; k >= k_lo; --k)
+    if ((rc = step(c, kAdjoint, k, tab, nsh, pb, nullptr, c->dscr, c->acc,
+                   d2_n0)))
+      return rc;
+  return BRLS_OK;
+}
+
+// Checkpoint mode: for each segment, last first, restore the background at
+// the segment start, recompute the segment's Born-source frames, then run
+// the adjoint steps that consume them.
+int adjoint_segments(brls_ctx* c, const ShotDev* tab, int nsh, int pb,
+                     int nt) {
+  int rc;
+  for (int seg = nseg_of(c, nt) - 1; seg >= 0; --seg) {
+    const int n0 = seg * c->ckpt_k;
+    const int n1 = std::min(n0 + c->ckpt_k, nt - 1);
+    HIPCHECK(c, launch_ckpt(tab, nsh, n0, seg, c->fs, 1, c->st));
+    for (int n = n0; n < n1; ++n)
+      if ((rc = step(c, kBackground, n, tab, nsh, pb, nullptr, nullptr,
+                     nullptr, n0, 1)))
+        return rc;
+    if ((rc = adjoint_steps(c, tab, nsh, pb, n1, n0 + 1, n0))) return rc;
+  }
   return BRLS_OK;
 }
 
@@ -361,16 +428,16 @@ int enqueue_adjoint(brls_ctx* c, int batched) {
   if ((rc = zero_fields(c))) return rc;
   HIPCHECK(c, launch_fill_f64(c->acc, ngroups * c->mplane, 0.0, c->st));
   if (!batched) {
-    for (int k = 0; k < nsh; ++k)
-      for (int n = c->slots[c->order[k]].nt - 1; n >= 1; --n)
-        if ((rc = step(c, kAdjoint, n, c->tab_dev + k, 1, 1, nullptr,
-                       c->dscr, c->acc)))
-          return rc;
+    for (int k = 0; k < nsh; ++k) {
+      const int nt = c->slots[c->order[k]].nt;
+      rc = c->ckpt_k ? adjoint_segments(c, c->tab_dev + k, 1, 1, nt)
+                     : adjoint_steps(c, c->tab_dev + k, 1, 1, nt - 1, 1, 0);
+      if (rc) return rc;
+    }
   } else {
-    for (int n = ntm - 1; n >= 1; --n)
-      if ((rc = step(c, kAdjoint, n, c->tab_dev, nsh, pb, nullptr, c->dscr,
-                     c->acc)))
-        return rc;
+    rc = c->ckpt_k ? adjoint_segments(c, c->tab_dev, nsh, pb, ntm)
+                   : adjoint_steps(c, c->tab_dev, nsh, pb, ntm - 1, 1, 0);
+    if (rc) return rc;
   }
   HIPCHECK(c, launch_adj_finalize(c->acc, ngroups, c->geo, c->wp, c->gbuf,
                                   c->st));
@@ -388,7 +455,7 @@ int run_op(brls_ctx* c, int op) {
                        : enqueue_adjoint(c, c->exec == BRLS_EXEC_BATCHED);
   const int nsh = (int)c->order.size();
   const GraphKey key(op, nsh, std::min(c->per_block, nsh), c->variant,
-                     nt_max_of(c, c->order));
+                     nt_max_of(c, c->order), c->resident_grid);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     const bool was_timing = c->timing;
@@ -541,6 +608,11 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   }
   set_variant_geo(c, 0);
   c->mplane = mpts;
+  if (g.ckpt_interval < 0)
+    c->ckpt_k = std::max(1, (int)std::ceil(std::sqrt((double)g.nt_max)));
+  else
+    c->ckpt_k = g.ckpt_interval;
+  if (c->ckpt_k) c->nseg_max = (g.nt_max - 1 + c->ckpt_k - 1) / c->ckpt_k;
   c->seg = round_up((int)std::min<int64_t>((int64_t)g.nt_max * g.nrec_max,
                                            (int64_t)1 << 30),
                     64);
@@ -553,7 +625,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
     return rc;                                      \
   }
   ALLOC(c->wp, c->fs);
-  ALLOC(c->fields_all, (int64_t)g.q_max * 3 * c->fs);
+  ALLOC(c->fields_all, field_floats(c));
   ALLOC(c->m, mpts);
   ALLOC(c->p, mpts);
   ALLOC(c->s, mpts);
@@ -573,8 +645,15 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   for (int i = 0; i < g.q_max; ++i) {
     Slot& sl = c->slots[i];
     sl.fields = c->fields_all + (int64_t)i * 3 * c->fs;
+    if (c->ckpt_k)
+      sl.bgf = c->fields_all + ((int64_t)g.q_max + i) * 3 * c->fs;
     sl.dat_off = (int64_t)i * c->seg;
-    ALLOC(sl.d2, (int64_t)(g.nt_max - 1) * mpts);
+    if (c->ckpt_k) {
+      ALLOC(sl.ck, (int64_t)c->nseg_max * 2 * c->fs);
+      ALLOC(sl.segd2, (int64_t)c->ckpt_k * mpts);
+    } else {
+      ALLOC(sl.d2, (int64_t)(g.nt_max - 1) * mpts);
+    }
     ALLOC(sl.wav, g.nt_max);
     ALLOC(sl.rptr, c->ntiles_max + 1);
     ALLOC(sl.rent, g.nrec_max);
@@ -594,8 +673,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   auto init = [&]() -> int {
     HIPCHECK(c, hipMemcpy(c->wp, wh.data(), sizeof(float) * wh.size(),
                           hipMemcpyHostToDevice));
-    HIPCHECK(c, launch_fill_f32(c->fields_all, (int64_t)g.q_max * 3 * c->fs,
-                                0.f, c->st));
+    HIPCHECK(c, launch_fill_f32(c->fields_all, field_floats(c), 0.f, c->st));
     HIPCHECK(c, launch_fill_f32(c->m, mpts, 0.f, c->st));
     for (float* v : {c->dobs, c->r, c->q, c->dscr})
       HIPCHECK(c, launch_fill_f32(v, (int64_t)g.q_max * c->seg, 0.f, c->st));
@@ -892,12 +970,14 @@ int brls_tile_count(int32_t* n) {
   return BRLS_OK;
 }
 
-int brls_tile_info(int32_t v, int32_t* tx, int32_t* tz, int32_t* pb) {
+int brls_tile_info(int32_t v, int32_t* tx, int32_t* tz, int32_t* rows,
+                   int32_t* pipelined) {
   if (v < 0 || v >= tile_shape_count()) return BRLS_EINVAL;
   const TileShape s = tile_shape(v);
   if (tx) *tx = s.tx;
   if (tz) *tz = s.tz;
-  if (pb) *pb = s.ntz;
+  if (rows) *rows = s.ntz;
+  if (pipelined) *pipelined = s.pipe;
   return BRLS_OK;
 }
 
@@ -950,10 +1030,13 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
   HIPCHECK(c, hipEventCreate(&e1));
   float best_ms = 1e30f;
   int best_v = c->variant, best_pb = c->per_block;
+  int best_rg = c->resident_grid;
   for (int v = 0; v < tile_shape_count(); ++v) {
-    for (int pb = 1; pb <= 8; pb *= 2) {
+    for (int trial = 0; trial < 8; ++trial) {
+      const int pb = 1 << (trial >> 1), rg = trial & 1;
       if (pb > nsh && pb > 1) break;
       if ((rc = set_tile_impl(c, v, pb))) return rc;
+      c->resident_grid = rg;
       HIPCHECK(c, hipEventRecord(e0, c->st));
       if ((rc = enqueue_born(c, 1)) || (rc = enqueue_adjoint(c, 1))) return rc;
       HIPCHECK(c, hipEventRecord(e1, c->st));
@@ -964,12 +1047,14 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
         best_ms = ms;
         best_v = v;
         best_pb = pb;
+        best_rg = rg;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->exec = saved_exec;
+  c->resident_grid = best_rg;
   if ((rc = set_tile_impl(c, best_v, best_pb))) return rc;
   if (best) *best = best_v;
   return BRLS_OK;
@@ -979,6 +1064,18 @@ int brls_get_tile(const brls_ctx* c, int32_t* variant, int32_t* per_block) {
   if (!c) return BRLS_EINVAL;
   if (variant) *variant = c->variant;
   if (per_block) *per_block = c->per_block;
+  return BRLS_OK;
+}
+
+int brls_set_resident_grid(brls_ctx* c, int32_t enable) {
+  if (!c) return BRLS_EINVAL;
+  c->resident_grid = enable != 0;
+  return BRLS_OK;
+}
+
+int brls_get_resident_grid(const brls_ctx* c, int32_t* enable) {
+  if (!c || !enable) return BRLS_EINVAL;
+  *enable = c->resident_grid;
   return BRLS_OK;
 }
 

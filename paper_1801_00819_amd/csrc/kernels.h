@@ -9,6 +9,7 @@ namespace brls {
 
 struct TileShape {
   int tx, tz, ntz;  // tile width (x), tile height (z), thread rows
+  int pipe;         // next shot's loads issued before computing the current
 };
 
 int tile_shape_count();
@@ -22,6 +23,9 @@ hipError_t launch_born_last(const ShotDev* tab, int nshots, int nrec_max,
 hipError_t launch_adj_finalize(const double* acc, int ngroups,
                                const Geo2D& g, const float* wp, float* out,
                                hipStream_t st);
+// Background checkpoint save (restore = 0) / restore (1) for all shots.
+hipError_t launch_ckpt(const ShotDev* tab, int nshots, int n0, int seg,
+                       int64_t fs, int restore, hipStream_t st);
 
 // Vector kernels (blas.hip). Sums are accumulated in float64 in a fixed
 // order (per-block partials, then one block), so results are deterministic.

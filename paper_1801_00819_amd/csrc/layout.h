@@ -34,18 +34,18 @@ struct StencilW {
 // Per-shot state of a window slot, read by the kernels through a device
 // table in window order.
 struct ShotDev {
-  float* u0;        // displacement, even time levels (storage layout)
-  float* u1;        // displacement, odd time levels
-  float* v;         // difference field, updated in place
-  float* d2;        // Born source cache: [nt-1][nz][nx] (model region)
-  const int* rptr;  // receivers per tile: CSR offsets [ntiles + 1]
-  const int2* rent; // (local index lz*TX + lx, receiver index)
-  const int* rsidx; // storage index of each receiver
-  const float* wav; // h^2 * source wavelet [nt]
-  int64_t dat_off;  // offset of this shot's [nt][nrec] segment in data vectors
+  float* f[3];       // propagated field: u (even levels), u (odd levels), v
+  float* b[3];       // background field (same layout); may alias f
+  float* d2;         // Born-source frames [..][nz][nx]; frame index n - d2_n0
+  float* ck;         // background checkpoints [seg][u | v][field] or null
+  const int* rptr;   // receivers per tile: CSR offsets [ntiles + 1]
+  const int2* rent;  // (local index lz*TX + lx, receiver index)
+  const int* rsidx;  // storage index of each receiver
+  const float* wav;  // h^2 * source wavelet [nt]
+  int64_t dat_off;   // offset of this shot's [nt][nrec] segment in data vectors
   int nt;
   int nrec;
-  int src_z, src_x; // padded grid position of the source
+  int src_z, src_x;  // padded grid position of the source
 };
 
 struct Geo2D {
@@ -59,7 +59,14 @@ struct Geo2D {
   StencilW w;
 };
 
-enum StepMode { kBackground = 0, kBorn = 1, kAdjoint = 2 };
+// kBackground: advance the background field b with the source; optionally
+//              store its Born source (the increment) as frame n.
+// kBorn:       advance f with source -m * frame n.
+// kBornFused:  advance b and f together, the Born source taken from b's
+//              increment on the fly (no stored frames).
+// kAdjoint:    advance f backward (output level n) with the residual
+//              injected at the receivers; image += -frame(n-1) * f^n.
+enum StepMode { kBackground = 0, kBorn = 1, kAdjoint = 2, kBornFused = 3 };
 
 struct StepArgs {
   Geo2D g;
@@ -69,6 +76,10 @@ struct StepArgs {
   int ngroups;         // ceil(nshots / per_block)
   int n;               // time level: input level (background, Born) or
                        // output level k (adjoint)
+  int d2_n0;           // time level of stored frame 0
+  int write_d2;        // background: store frames
+  int resident_grid;   // launch only as many blocks as fit at once (each
+                       // loops over work items); else one block per item
   const float* wp;     // W' = v^2 dt^2 / h^2, storage layout
   const float* pm;     // Born: model perturbation [nz][nx]
   float* dat;          // Born: output data base; adjoint: input residual base

@@ -28,13 +28,14 @@ def oracle_problem(w, shots=None):
 
 
 def open_ctx(w, lam=0.0, q_max=None, nt_max=None, nrec_max=None,
-             device=False):
+             device=False, ckpt_interval=0):
     import paper_1801_00819_amd as P
     q_max = q_max or len(w.shots)
     nt_max = nt_max or max(s.nt for s in w.shots)
     nrec_max = nrec_max or max(s.nrec for s in w.shots)
     return P.brls_open(w.ndim, w.nz, w.ny, w.nx, w.nb, nt_max, nrec_max,
-                       q_max, w.h, w.dt, lam, vel32(w), device=device)
+                       q_max, w.h, w.dt, lam, vel32(w), device=device,
+                       ckpt_interval=ckpt_interval)
 
 
 def add_shot(ctx, w, i, data=None, sid=None):
