@@ -66,7 +66,7 @@ extern "C" {
 typedef struct brls_ctx brls_ctx;
 
 typedef struct {
-  int32_t ndim;       /* 2 (implemented); 3 is rejected with BRLS_EINVAL */
+  int32_t ndim;       /* 2 or 3 */
   int32_t nz, ny, nx; /* model grid (ny ignored in 2-D) */
   int32_t nb;         /* absorbing cells on every face, >= 1 */
   int32_t nt_max;     /* largest number of time samples of any shot */
@@ -112,8 +112,9 @@ typedef struct {
  * stream: hipStream_t to order all work on; NULL gives the context a private
  * stream that synchronises with the null stream (graphs cannot capture the
  * null stream itself).
- * Checks CFL stability of the scheme (v_max dt / h below the 2-D limit
- * 0.5546 of the 8th-order stencil) and returns BRLS_EINVAL otherwise.
+ * Checks CFL stability of the scheme (v_max dt / h below 0.5546 in 2-D and
+ * 0.4529 in 3-D for the 8th-order stencil) and returns BRLS_EINVAL
+ * otherwise.
  * Allocates the device state for q_max shots (see brls_memory_bytes). */
 int brls_open(const brls_grid* g, const float* vel, void* stream,
               brls_ctx** out);
@@ -180,6 +181,11 @@ int brls_set_exec(brls_ctx* ctx, int32_t mode);
  * issues the next shot's loads before computing the current one. */
 int brls_set_tile(brls_ctx* ctx, int32_t variant);
 int brls_tile_count(int32_t* n);
+/* 3-D variants: XY tile tx x ty and the shots a block advances together
+ * (a 3-D context's shots per block follow its variant). */
+int brls_tile3_count(int32_t* n);
+int brls_tile3_info(int32_t variant, int32_t* tx, int32_t* ty,
+                    int32_t* shots);
 int brls_tile_info(int32_t variant, int32_t* tx, int32_t* tz,
                    int32_t* thread_rows, int32_t* pipelined);
 

@@ -281,3 +281,15 @@ def tile_variants():
                                        ctypes.byref(r), ctypes.byref(pp)))
         out.append((tx.value, tz.value, r.value, pp.value))
     return out
+
+
+def tile3_variants():
+    n = ctypes.c_int32()
+    L.check(L.lib().brls_tile3_count(ctypes.byref(n)))
+    out = []
+    for v in range(n.value):
+        tx, ty, sb = (ctypes.c_int32() for _ in range(3))
+        L.check(L.lib().brls_tile3_info(v, ctypes.byref(tx), ctypes.byref(ty),
+                                        ctypes.byref(sb)))
+        out.append((tx.value, ty.value, sb.value))
+    return out

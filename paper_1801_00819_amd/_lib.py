@@ -92,6 +92,9 @@ SIGNATURES = [
     ("brls_tile_info", _I32, [_I32, ctypes.POINTER(_I32),
                               ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                               ctypes.POINTER(_I32)]),
+    ("brls_tile3_count", _I32, [ctypes.POINTER(_I32)]),
+    ("brls_tile3_info", _I32, [_I32, ctypes.POINTER(_I32),
+                               ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("brls_set_shots_per_block", _I32, [_VP, _I32]),
     ("brls_get_tile", _I32, [_VP, ctypes.POINTER(_I32),
                              ctypes.POINTER(_I32)]),

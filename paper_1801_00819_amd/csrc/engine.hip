@@ -37,6 +37,10 @@ constexpr double kW1 = 8.0 / 5.0, kW2 = -1.0 / 5.0, kW3 = 8.0 / 315.0,
 // S = 205/72 + 2 (8/5 + 1/5 + 8/315 + 1/560) at the Nyquist wavenumber, and
 // leapfrog needs C^2 * 2S <= 4, i.e. C <= 2 / sqrt(2 S).
 constexpr double kCfl2D = 0.5546;
+// Same for 3-D: C <= 2 / sqrt(3 S).
+constexpr double kCfl3D = 0.4529;
+// z planes per 3-D work item
+constexpr int kZChunk = 32;
 
 thread_local std::string g_open_error;
 
@@ -45,7 +49,7 @@ struct Slot {
   int64_t id = 0;
   int64_t seq = 0;
   int nt = 0, nrec = 0;
-  int sz = 0, sx = 0;
+  int sz = 0, sy = 0, sx = 0;
   double f0 = 0.0;
   std::vector<int32_t> rec;  // host copy (z, y, x)
   bool bg_ready = false;
@@ -82,7 +86,9 @@ struct brls_ctx {
   hipStream_t st = nullptr;
   bool own_stream = false;
   int device = 0;
+  int ndim = 2;
   Geo2D geo{};
+  Geo3D geo3{};
   int variant = 0;
   int per_block = 4;
   int resident_grid = 0;
@@ -166,35 +172,68 @@ hipMemcpyKind out_kind(const brls_ctx* c) {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+int variant_count(const brls_ctx* c) {
+  return c->ndim == 3 ? tile_shape3_count() : tile_shape_count();
+}
+
 void set_variant_geo(brls_ctx* c, int v) {
-  const TileShape ts = tile_shape(v);
-  Geo2D& g = c->geo;
-  g.ntx = (g.px - g.x_org + ts.tx - 1) / ts.tx;
-  g.ntz = (g.pz + ts.tz - 1) / ts.tz;
-  g.ntiles = g.ntx * g.ntz;
+  if (c->ndim == 3) {
+    const TileShape3 ts = tile_shape3(v);
+    Geo3D& g = c->geo3;
+    g.ntx = (g.px - g.x_org + ts.tx - 1) / ts.tx;
+    g.nty = (g.py + ts.ty - 1) / ts.ty;
+    g.tzc = kZChunk;
+    g.ntz = (g.pz + g.tzc - 1) / g.tzc;
+    g.ntiles = g.ntx * g.nty * g.ntz;
+  } else {
+    const TileShape ts = tile_shape(v);
+    Geo2D& g = c->geo;
+    g.ntx = (g.px - g.x_org + ts.tx - 1) / ts.tx;
+    g.ntz = (g.pz + ts.tz - 1) / ts.tz;
+    g.ntiles = g.ntx * g.ntz;
+  }
   c->variant = v;
 }
 
-// Per-tile receiver lists of one slot for the current tile shape.
+// CSR bins of the receiver lists for the current tile shape.
+int receiver_bins(const brls_ctx* c) {
+  if (c->ndim == 3) return c->geo3.ntx * c->geo3.nty * c->geo3.pz;
+  return c->geo.ntiles;
+}
+
+// Per-tile receiver lists of one slot for the current tile shape. 2-D: one
+// bin per tile, local index lz * TX + lx. 3-D: one bin per (XY tile, padded
+// z), local index ly * TX + lx.
 int build_receiver_tiles(brls_ctx* c, Slot& sl) {
-  const TileShape ts = tile_shape(c->variant);
-  const Geo2D& g = c->geo;
-  std::vector<int> cnt(g.ntiles + 1, 0), tileof(sl.nrec), loc(sl.nrec);
+  const int nbins = receiver_bins(c);
+  std::vector<int> cnt(nbins + 1, 0), binof(sl.nrec), loc(sl.nrec);
   for (int j = 0; j < sl.nrec; ++j) {
-    const int pz = sl.rec[3 * j] + g.nb, px = sl.rec[3 * j + 2] + g.nb;
-    const int tzi = pz / ts.tz, txi = (px - g.x_org) / ts.tx;
-    tileof[j] = tzi * g.ntx + txi;
-    loc[j] = (pz - tzi * ts.tz) * ts.tx + (px - g.x_org - txi * ts.tx);
-    cnt[tileof[j] + 1]++;
+    if (c->ndim == 3) {
+      const TileShape3 ts = tile_shape3(c->variant);
+      const Geo3D& g = c->geo3;
+      const int pz = sl.rec[3 * j] + g.nb, py = sl.rec[3 * j + 1] + g.nb,
+                px = sl.rec[3 * j + 2] + g.nb;
+      const int tyi = py / ts.ty, txi = (px - g.x_org) / ts.tx;
+      binof[j] = (tyi * g.ntx + txi) * g.pz + pz;
+      loc[j] = (py - tyi * ts.ty) * ts.tx + (px - g.x_org - txi * ts.tx);
+    } else {
+      const TileShape ts = tile_shape(c->variant);
+      const Geo2D& g = c->geo;
+      const int pz = sl.rec[3 * j] + g.nb, px = sl.rec[3 * j + 2] + g.nb;
+      const int tzi = pz / ts.tz, txi = (px - g.x_org) / ts.tx;
+      binof[j] = tzi * g.ntx + txi;
+      loc[j] = (pz - tzi * ts.tz) * ts.tx + (px - g.x_org - txi * ts.tx);
+    }
+    cnt[binof[j] + 1]++;
   }
-  for (int t = 0; t < g.ntiles; ++t) cnt[t + 1] += cnt[t];
+  for (int t = 0; t < nbins; ++t) cnt[t + 1] += cnt[t];
   std::vector<int2> ent(std::max(sl.nrec, 1));
   std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
   for (int j = 0; j < sl.nrec; ++j) {
     int2 e;
     e.x = loc[j];
     e.y = j;
-    ent[fillp[tileof[j]]++] = e;
+    ent[fillp[binof[j]]++] = e;
   }
   HIPCHECK(c, hipMemcpyAsync(sl.rptr, cnt.data(), sizeof(int) * cnt.size(),
                              hipMemcpyHostToDevice, c->st));
@@ -202,6 +241,10 @@ int build_receiver_tiles(brls_ctx* c, Slot& sl) {
                              hipMemcpyHostToDevice, c->st));
   HIPCHECK(c, hipStreamSynchronize(c->st));
   return BRLS_OK;
+}
+
+int64_t store_index(const brls_ctx* c, int z, int y, int x) {
+  return c->ndim == 3 ? sidx3(c->geo3, z, y, x) : sidx2(c->geo, z, x);
 }
 
 ShotDev shot_dev(const brls_ctx* c, const Slot& sl) {
@@ -219,8 +262,9 @@ ShotDev shot_dev(const brls_ctx* c, const Slot& sl) {
   d.dat_off = sl.dat_off;
   d.nt = sl.nt;
   d.nrec = sl.nrec;
-  d.src_z = sl.sz + c->geo.nb;
-  d.src_x = sl.sx + c->geo.nb;
+  d.src_z = sl.sz + c->g.nb;
+  d.src_y = c->ndim == 3 ? sl.sy + c->g.nb : 0;
+  d.src_x = sl.sx + c->g.nb;
   return d;
 }
 
@@ -271,6 +315,7 @@ int timed_end(brls_ctx* c, Timer* t) {
 StepArgs base_args(const brls_ctx* c) {
   StepArgs a{};
   a.g = c->geo;
+  a.g3 = c->geo3;
   a.wp = c->wp;
   a.resident_grid = c->resident_grid;
   return a;
@@ -297,7 +342,8 @@ int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
                                               : kTBorn,
                        &t);
   if (rc) return rc;
-  HIPCHECK(c, launch_step2d(c->variant, mode, a, c->st));
+  HIPCHECK(c, c->ndim == 3 ? launch_step3d(c->variant, mode, a, c->st)
+                           : launch_step2d(c->variant, mode, a, c->st));
   return timed_end(c, &t);
 }
 
@@ -439,8 +485,10 @@ int enqueue_adjoint(brls_ctx* c, int batched) {
                    : adjoint_steps(c, c->tab_dev, nsh, pb, ntm - 1, 1, 0);
     if (rc) return rc;
   }
-  HIPCHECK(c, launch_adj_finalize(c->acc, ngroups, c->geo, c->wp, c->gbuf,
-                                  c->st));
+  HIPCHECK(c, c->ndim == 3 ? launch_adj_finalize3(c->acc, ngroups, c->geo3,
+                                                   c->wp, c->gbuf, c->st)
+                           : launch_adj_finalize(c->acc, ngroups, c->geo,
+                                                 c->wp, c->gbuf, c->st));
   return BRLS_OK;
 }
 
@@ -543,23 +591,28 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   *out = nullptr;
   if (!gin || !vel) return fail(nullptr, BRLS_EINVAL, "grid or vel is NULL");
   const brls_grid g = *gin;
-  if (g.ndim != 2)
-    return fail(nullptr, BRLS_EINVAL, "ndim %d not supported (2-D only)",
-                g.ndim);
-  if (g.nz < 1 || g.nx < 1 || g.nb < 1 || g.nt_max < 2 || g.nrec_max < 1 ||
-      g.q_max < 1 || !(g.h > 0) || !(g.dt > 0) || !(g.lambda >= 0))
+  if (g.ndim != 2 && g.ndim != 3)
+    return fail(nullptr, BRLS_EINVAL, "ndim must be 2 or 3, got %d", g.ndim);
+  const int ny = g.ndim == 3 ? g.ny : 1;
+  if (g.nz < 1 || ny < 1 || g.nx < 1 || g.nb < 1 || g.nt_max < 2 ||
+      g.nrec_max < 1 || g.q_max < 1 || !(g.h > 0) || !(g.dt > 0) ||
+      !(g.lambda >= 0))
     return fail(nullptr, BRLS_EINVAL, "invalid grid sizes or spacing");
-  const int64_t mpts = (int64_t)g.nz * g.nx;
+  const int64_t mpts = (int64_t)g.nz * ny * g.nx;
+  if (mpts >= ((int64_t)1 << 30))
+    return fail(nullptr, BRLS_EINVAL, "model of %lld points is too large",
+                (long long)mpts);
   double vmax = 0.0;
   for (int64_t i = 0; i < mpts; ++i) {
     if (!(vel[i] > 0.f) || !std::isfinite(vel[i]))
       return fail(nullptr, BRLS_EINVAL, "velocity must be finite and > 0");
     vmax = std::max(vmax, (double)vel[i]);
   }
-  if (vmax * g.dt / g.h > kCfl2D)
+  const double cfl = g.ndim == 3 ? kCfl3D : kCfl2D;
+  if (vmax * g.dt / g.h > cfl)
     return fail(nullptr, BRLS_EINVAL,
                 "unstable: v_max dt / h = %.4f exceeds %.4f",
-                vmax * g.dt / g.h, kCfl2D);
+                vmax * g.dt / g.h, cfl);
   hipDeviceProp_t prop;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -583,30 +636,60 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
     c->own_stream = true;
   }
   c->device = dev;
-  Geo2D& geo = c->geo;
-  geo.nz = g.nz;
-  geo.nx = g.nx;
-  geo.nb = g.nb;
-  geo.pz = g.nz + 2 * g.nb;
-  geo.px = g.nx + 2 * g.nb;
-  geo.x_org = (g.nb % 32 == 0) ? 0 : (g.nb % 32) - 32;
-  geo.xoff = 32 - geo.x_org;
-  geo.pitch = round_up(geo.xoff + round_up(geo.px - geo.x_org, 128) + kGhost,
-                       32);
-  c->rows_alloc = round_up(geo.pz, 64) + 2 * kGhost;
-  c->fs = (int64_t)c->rows_alloc * geo.pitch;
+  c->ndim = g.ndim;
   const double eta_max = 3.0 * vmax * std::log(1000.0) / (2.0 * g.nb * g.h);
-  geo.eta_scale = (float)(eta_max * g.dt / 2.0 / ((double)g.nb * g.nb));
-  geo.w.c1 = (float)kW1;
-  geo.w.c2 = (float)kW2;
-  geo.w.c3 = (float)kW3;
-  geo.w.c4 = (float)kW4;
-  c->ntiles_max = 0;
-  for (int v = 0; v < tile_shape_count(); ++v) {
+  const float eta_scale =
+      (float)(eta_max * g.dt / 2.0 / ((double)g.nb * g.nb));
+  const StencilW sw = {(float)kW1, (float)kW2, (float)kW3, (float)kW4};
+  const int x_org = (g.nb % 32 == 0) ? 0 : (g.nb % 32) - 32;
+  const int px = g.nx + 2 * g.nb;
+  // x: first model column on a 128-byte boundary; room for every tile width
+  // (all divide 128) plus the 4-cell ring
+  const int pitch = round_up(32 - x_org + round_up(px - x_org, 128) + kGhost,
+                             32);
+  if (g.ndim == 3) {
+    Geo3D& geo = c->geo3;
+    geo.nz = g.nz;
+    geo.ny = ny;
+    geo.nx = g.nx;
+    geo.nb = g.nb;
+    geo.pz = g.nz + 2 * g.nb;
+    geo.py = ny + 2 * g.nb;
+    geo.px = px;
+    geo.x_org = x_org;
+    geo.xoff = 32 - x_org;
+    geo.pitch = pitch;
+    // y: room for tiles of up to 8 rows plus the ring; z: the ring (z chunks
+    // stop at the padded grid)
+    const int rows = round_up(geo.py, 8) + 2 * kGhost;
+    geo.plane = rows * pitch;
+    c->rows_alloc = geo.pz + 2 * kGhost;
+    c->fs = (int64_t)c->rows_alloc * geo.plane;
+    geo.eta_scale = eta_scale;
+    geo.w = sw;
+  } else {
+    Geo2D& geo = c->geo;
+    geo.nz = g.nz;
+    geo.nx = g.nx;
+    geo.nb = g.nb;
+    geo.pz = g.nz + 2 * g.nb;
+    geo.px = px;
+    geo.x_org = x_org;
+    geo.xoff = 32 - x_org;
+    geo.pitch = pitch;
+    // z: room for tiles of up to 64 rows plus the ring
+    c->rows_alloc = round_up(geo.pz, 64) + 2 * kGhost;
+    c->fs = (int64_t)c->rows_alloc * geo.pitch;
+    geo.eta_scale = eta_scale;
+    geo.w = sw;
+  }
+  c->ntiles_max = 0;  // largest receiver-bin count over tile variants
+  for (int v = 0; v < variant_count(c); ++v) {
     set_variant_geo(c, v);
-    c->ntiles_max = std::max(c->ntiles_max, geo.ntiles);
+    c->ntiles_max = std::max(c->ntiles_max, receiver_bins(c));
   }
   set_variant_geo(c, 0);
+  if (g.ndim == 3) c->per_block = tile_shape3(0).sb;
   c->mplane = mpts;
   if (g.ckpt_interval < 0)
     c->ckpt_k = std::max(1, (int)std::ceil(std::sqrt((double)g.nt_max)));
@@ -663,13 +746,17 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   // W' = v^2 dt^2 / h^2 on the padded grid (velocity edge-replicated)
   std::vector<float> wh((size_t)c->fs, 0.f);
   const double s2 = g.dt * g.dt / (g.h * g.h);
-  for (int z = 0; z < geo.pz; ++z)
-    for (int x = 0; x < geo.px; ++x) {
-      const int mz = std::min(std::max(z - g.nb, 0), g.nz - 1);
-      const int mx = std::min(std::max(x - g.nb, 0), g.nx - 1);
-      const double v = vel[(int64_t)mz * g.nx + mx];
-      wh[sidx2(geo, z, x)] = (float)(v * v * s2);
-    }
+  const int pz = g.nz + 2 * g.nb, py = g.ndim == 3 ? ny + 2 * g.nb : 1;
+  for (int z = 0; z < pz; ++z)
+    for (int y = 0; y < py; ++y)
+      for (int x = 0; x < px; ++x) {
+        const int mz = std::min(std::max(z - g.nb, 0), g.nz - 1);
+        const int my = g.ndim == 3 ? std::min(std::max(y - g.nb, 0), ny - 1)
+                                   : 0;
+        const int mx = std::min(std::max(x - g.nb, 0), g.nx - 1);
+        const double v = vel[((int64_t)mz * ny + my) * g.nx + mx];
+        wh[store_index(c, z, y, x)] = (float)(v * v * s2);
+      }
   auto init = [&]() -> int {
     HIPCHECK(c, hipMemcpy(c->wp, wh.data(), sizeof(float) * wh.size(),
                           hipMemcpyHostToDevice));
@@ -724,12 +811,16 @@ int brls_update(brls_ctx* c, const brls_shot* sh) {
       sh->nrec > c->g.nrec_max || !(sh->f0 > 0) || !sh->rec)
     return fail(c, BRLS_EINVAL, "shot %lld: bad nt, nrec, f0 or receivers",
                 (long long)sh->id);
-  if (sh->sz < 0 || sh->sz >= c->g.nz || sh->sx < 0 || sh->sx >= c->g.nx)
+  const int ny = c->ndim == 3 ? c->g.ny : 1;
+  const int ssy = c->ndim == 3 ? sh->sy : 0;
+  if (sh->sz < 0 || sh->sz >= c->g.nz || sh->sx < 0 || sh->sx >= c->g.nx ||
+      ssy < 0 || ssy >= ny)
     return fail(c, BRLS_EINVAL, "shot %lld: source outside the model",
                 (long long)sh->id);
   for (int j = 0; j < sh->nrec; ++j) {
     const int z = sh->rec[3 * j], x = sh->rec[3 * j + 2];
-    if (z < 0 || z >= c->g.nz || x < 0 || x >= c->g.nx)
+    const int y = c->ndim == 3 ? sh->rec[3 * j + 1] : 0;
+    if (z < 0 || z >= c->g.nz || x < 0 || x >= c->g.nx || y < 0 || y >= ny)
       return fail(c, BRLS_EINVAL, "shot %lld: receiver %d outside the model",
                   (long long)sh->id, j);
   }
@@ -752,9 +843,12 @@ int brls_update(brls_ctx* c, const brls_shot* sh) {
   sl.nt = sh->nt;
   sl.nrec = sh->nrec;
   sl.sz = sh->sz;
+  sl.sy = ssy;
   sl.sx = sh->sx;
   sl.f0 = sh->f0;
   sl.rec.assign(sh->rec, sh->rec + 3 * sh->nrec);
+  if (c->ndim != 3)
+    for (int j = 0; j < sh->nrec; ++j) sl.rec[3 * j + 1] = 0;
   // h^2 * Ricker(f0), delay 1.5/f0: the point source of strength h^d f(t)
   // scaled to the W' = v^2 dt^2 / h^2 of the kernels.
   std::vector<float> wav(sh->nt);
@@ -766,8 +860,9 @@ int brls_update(brls_ctx* c, const brls_shot* sh) {
   }
   std::vector<int> rs(sh->nrec);
   for (int j = 0; j < sh->nrec; ++j)
-    rs[j] = (int)sidx2(c->geo, sl.rec[3 * j] + c->geo.nb,
-                       sl.rec[3 * j + 2] + c->geo.nb);
+    rs[j] = (int)store_index(c, sl.rec[3 * j] + c->g.nb,
+                             sl.rec[3 * j + 1] + (c->ndim == 3 ? c->g.nb : 0),
+                             sl.rec[3 * j + 2] + c->g.nb);
   HIPCHECK(c, hipMemcpyAsync(sl.wav, wav.data(), 4 * wav.size(),
                              hipMemcpyHostToDevice, c->st));
   HIPCHECK(c, hipMemcpyAsync(sl.rsidx, rs.data(), 4 * rs.size(),
@@ -970,6 +1065,21 @@ int brls_tile_count(int32_t* n) {
   return BRLS_OK;
 }
 
+int brls_tile3_count(int32_t* n) {
+  if (!n) return BRLS_EINVAL;
+  *n = tile_shape3_count();
+  return BRLS_OK;
+}
+
+int brls_tile3_info(int32_t v, int32_t* tx, int32_t* ty, int32_t* shots) {
+  if (v < 0 || v >= tile_shape3_count()) return BRLS_EINVAL;
+  const TileShape3 s = tile_shape3(v);
+  if (tx) *tx = s.tx;
+  if (ty) *ty = s.ty;
+  if (shots) *shots = s.sb;
+  return BRLS_OK;
+}
+
 int brls_tile_info(int32_t v, int32_t* tx, int32_t* tz, int32_t* rows,
                    int32_t* pipelined) {
   if (v < 0 || v >= tile_shape_count()) return BRLS_EINVAL;
@@ -982,9 +1092,11 @@ int brls_tile_info(int32_t v, int32_t* tx, int32_t* tz, int32_t* rows,
 }
 
 static int set_tile_impl(brls_ctx* c, int v, int per_block) {
-  if (v < 0 || v >= tile_shape_count())
+  if (v < 0 || v >= variant_count(c))
     return fail(c, BRLS_EINVAL, "tile variant %d out of range", v);
   if (per_block < 1) per_block = 1;
+  // 3-D kernels advance a fixed number of shots per block together
+  if (c->ndim == 3) per_block = tile_shape3(v).sb;
   HIPCHECK(c, hipStreamSynchronize(c->st));
   const bool changed = v != c->variant;
   set_variant_geo(c, v);
@@ -1008,6 +1120,10 @@ int brls_set_tile(brls_ctx* c, int32_t variant) {
 int brls_set_shots_per_block(brls_ctx* c, int32_t per_block) {
   if (!c || per_block < 1)
     return fail(c, BRLS_EINVAL, "shots per block must be >= 1");
+  if (c->ndim == 3 && per_block != tile_shape3(c->variant).sb)
+    return fail(c, BRLS_EINVAL,
+                "3-D tile variant %d advances %d shots per block", c->variant,
+                tile_shape3(c->variant).sb);
   c->per_block = per_block;
   return BRLS_OK;
 }
@@ -1031,9 +1147,14 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
   float best_ms = 1e30f;
   int best_v = c->variant, best_pb = c->per_block;
   int best_rg = c->resident_grid;
-  for (int v = 0; v < tile_shape_count(); ++v) {
+  for (int v = 0; v < variant_count(c); ++v) {
     for (int trial = 0; trial < 8; ++trial) {
-      const int pb = 1 << (trial >> 1), rg = trial & 1;
+      int pb = 1 << (trial >> 1);
+      const int rg = trial & 1;
+      if (c->ndim == 3) {  // shots per block fixed by the variant
+        if (trial > 1) break;
+        pb = tile_shape3(v).sb;
+      }
       if (pb > nsh && pb > 1) break;
       if ((rc = set_tile_impl(c, v, pb))) return rc;
       c->resident_grid = rg;

@@ -15,6 +15,18 @@ struct TileShape {
 int tile_shape_count();
 TileShape tile_shape(int variant);
 
+struct TileShape3 {
+  int tx, ty;  // XY tile (threads)
+  int sb;      // shots per block, advanced together plane by plane
+};
+int tile_shape3_count();
+TileShape3 tile_shape3(int variant);
+hipError_t launch_step3d(int variant, int mode, const StepArgs& a,
+                         hipStream_t st);
+hipError_t launch_adj_finalize3(const double* acc, int ngroups,
+                                const Geo3D& g, const float* wp, float* out,
+                                hipStream_t st);
+
 // One time step for all shots of `a` (mode: StepMode).
 hipError_t launch_step2d(int variant, int mode, const StepArgs& a,
                          hipStream_t st);

@@ -36,7 +36,7 @@ struct StencilW {
 struct ShotDev {
   float* f[3];       // propagated field: u (even levels), u (odd levels), v
   float* b[3];       // background field (same layout); may alias f
-  float* d2;         // Born-source frames [..][nz][nx]; frame index n - d2_n0
+  float* d2;         // Born-source frames [..][model]; frame index n - d2_n0
   float* ck;         // background checkpoints [seg][u | v][field] or null
   const int* rptr;   // receivers per tile: CSR offsets [ntiles + 1]
   const int2* rent;  // (local index lz*TX + lx, receiver index)
@@ -46,6 +46,7 @@ struct ShotDev {
   int nt;
   int nrec;
   int src_z, src_x;  // padded grid position of the source
+  int src_y;         // (3-D)
 };
 
 struct Geo2D {
@@ -56,6 +57,23 @@ struct Geo2D {
   int x_org;         // padded x of the first tile column (<= 0)
   int ntx, ntz, ntiles;
   float eta_scale;   // eta_max * dt / 2 / nb^2
+  StencilW w;
+};
+
+// 3-D grid: padded point (z, y, x) sits at
+//     (z + 4) * plane + (y + 4) * pitch + x + xoff
+// with the same zero ring of 4 cells on every face.
+struct Geo3D {
+  int pz, py, px;      // padded grid
+  int nz, ny, nx, nb;  // model grid, sponge width
+  int pitch;           // storage row pitch (floats)
+  int plane;           // storage floats per z-plane
+  int xoff;            // storage column of padded x = 0
+  int x_org;           // padded x of the first tile column (<= 0)
+  int ntx, nty, ntz;   // tiles in x, y; z chunks
+  int tzc;             // planes per z chunk
+  int ntiles;          // ntx * nty * ntz
+  float eta_scale;     // eta_max * dt / 2 / nb^2
   StencilW w;
 };
 
@@ -70,6 +88,7 @@ enum StepMode { kBackground = 0, kBorn = 1, kAdjoint = 2, kBornFused = 3 };
 
 struct StepArgs {
   Geo2D g;
+  Geo3D g3;            // 3-D launches
   const ShotDev* tab;  // shots of this launch
   int nshots;          // shots in tab
   int per_block;       // shots handled by one block (sequentially)
@@ -88,6 +107,11 @@ struct StepArgs {
 
 __host__ __device__ inline int64_t sidx2(const Geo2D& g, int z, int x) {
   return (int64_t)(z + kGhost) * g.pitch + x + g.xoff;
+}
+
+__host__ __device__ inline int64_t sidx3(const Geo3D& g, int z, int y, int x) {
+  return (int64_t)(z + kGhost) * g.plane + (int64_t)(y + kGhost) * g.pitch +
+         x + g.xoff;
 }
 
 }  // namespace brls

@@ -38,9 +38,9 @@ def test_open_rejects_bad_grid_without_touching_the_device():
                     np.ones((1, 8), np.float32))
     assert e.value.code == -1 and "invalid grid" in str(e.value)
     with pytest.raises(P.BrlsError) as e:
-        P.brls_open(3, 8, 8, 8, 4, 10, 4, 1, 10.0, 1e-3, 0.0,
+        P.brls_open(4, 8, 8, 8, 4, 10, 4, 1, 10.0, 1e-3, 0.0,
                     np.ones((8, 8, 8), np.float32))
-    assert e.value.code == -1
+    assert e.value.code == -1 and "ndim" in str(e.value)
 
 
 def test_missing_library_fails_loudly(tmp_path):
