@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # tile variant and shots per block used without autotuning (and by the
 # counter runs): the autotuner's pick on this workload
 DEFAULT_TILE = (0, 2)
+DEFAULT_TILE3 = 1
 
 
 def parse():
@@ -49,6 +50,11 @@ def parse():
     ap.add_argument("--cpu-sample-nt", type=int, default=800)
     ap.add_argument("--only-steps", action="store_true",
                     help="time the steps only (for profiler runs)")
+    ap.add_argument("--workload", default="2d",
+                    choices=["2d", "3d", "autograd"],
+                    help="2d: the window chain (default); 3d: the batched "
+                         "3-D operator pair; autograd: differentiable Born "
+                         "with checkpointed backgrounds")
     ap.add_argument("--ops-only", action="store_true",
                     help="after setup run one 512 MiB device copy (the "
                          "counter calibration kernel) and one batched Born "
@@ -99,6 +105,199 @@ def ops_only(P, w, vel, m_true):
     log("ops-only: done")
 
 
+def bytes3d(kind, Q, ngroups, npad, nint, nrec):
+    """Algorithmic bytes of one batched 3-D step launch (float32), with the
+    background checkpointed and recomputed: the fused Born step advances two
+    fields (32 B per shot and padded point); the background recompute
+    advances one and writes its Born source on the model region; the
+    adjoint advances one and reads that source; per block group the medium
+    and the model vector (Born) or the float64 image accumulator (adjoint)."""
+    if kind == "born":
+        return Q * (32 * npad + 4 * nrec) + ngroups * (4 * npad + 4 * nint)
+    if kind == "background":
+        return Q * (16 * npad + 4 * nint) + ngroups * 4 * npad
+    return Q * (16 * npad + 4 * nint + 4 * nrec) + ngroups * (
+        4 * npad + 16 * nint)
+
+
+def bench_3d(args, P, synth, torch):
+    """3-D batching form: 256 x 320 x 320 model (296 x 360 x 360 padded),
+    one 8-shot window, 128 x 128 receivers, nt = 2000, background
+    checkpointed every ceil(sqrt(nt)) steps. Times one Born + adjoint pair
+    replayed from a graph against the plain per-shot launches."""
+    w = synth.config3()
+    Q = w.Q
+    nt, nrec = w.nt, w.shots[0].nrec
+    pz, py, px = (w.nz + 2 * w.nb, w.ny + 2 * w.nb, w.nx + 2 * w.nb)
+    npad, nint = pz * py * px, w.nz * w.ny * w.nx
+    vel = w.vel.astype(np.float32)
+    m = torch.from_numpy(w.m_true.astype(np.float32)).cuda()
+    ctx = P.brls_open(3, w.nz, w.ny, w.nx, w.nb, nt, nrec, Q, w.h, w.dt, 1.0,
+                      vel, device=True, ckpt_interval=-1)
+    for i in w.windows()[0]:
+        s = w.shots[i]
+        ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+    t = time.perf_counter()
+    if args.no_autotune:
+        ctx.set_tile(DEFAULT_TILE3)
+        ctx.apply_born(m)  # builds the background checkpoints
+    else:
+        ctx.autotune()
+    torch.cuda.synchronize()
+    log(f"3d: checkpoints + tuning {time.perf_counter() - t:.1f}s, tile "
+        f"{ctx.get_tile()} {P.tile3_variants()[ctx.get_tile()[0]]} "
+        f"resident grid {ctx.get_resident_grid()}")
+    res = {}
+    modes = [(P.BRLS_EXEC_GRAPH, "graph")]
+    if not args.no_plain:
+        modes.append((P.BRLS_EXEC_PLAIN, "plain"))
+    d = None
+    for mode, name in modes:
+        ctx.set_exec(mode)
+        if mode == P.BRLS_EXEC_GRAPH:
+            d = ctx.apply_born(m)
+            ctx.apply_adjoint(d)  # graph capture outside the timing
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        d = ctx.apply_born(m)
+        ctx.apply_adjoint(d)
+        torch.cuda.synchronize()
+        res[name] = time.perf_counter() - t
+        log(f"3d {name}: {res[name]:.2f}s")
+    ctx.set_exec(P.BRLS_EXEC_BATCHED)
+    ctx.kernel_timing(True)
+    ctx.apply_adjoint(ctx.apply_born(m))
+    ks = ctx.kernel_stats()
+    ctx.kernel_timing(False)
+    var, pb = ctx.get_tile()
+    ngroups = (Q + pb - 1) // pb
+    roof = {}
+    for kind, name in (("born", "born_step"), ("adjoint", "adjoint_step"),
+                       ("background", "background_step")):
+        n, ms = ks[name]
+        avg = ms / n / 1e3
+        b = bytes3d(kind, Q, ngroups, npad, nint, nrec)
+        roof[kind] = dict(avg_us=avg * 1e6, bytes=b, gbs=b / avg / 1e9)
+    mem = ctx.memory_bytes()
+    ctx.close()
+    pair = 2 * Q * npad * (nt - 1)
+    dom = max(roof, key=lambda k: roof[k]["avg_us"])
+    out = {
+        "metric": "Born+adjoint Gpt-updates/s",
+        "value": round(pair / res["graph"] / 1e9, 3),
+        "unit": "Gpt-updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(res["graph"] * 1e3, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "layered3d-256x320x320: one window of 8 "
+                               "shots, 128x128 receivers, nt=2000, one Born "
+                               "+ adjoint pair, background checkpointed "
+                               "(45 steps)",
+                   "padded_grid": [pz, py, px], "tile": [var, pb]},
+        "device_bytes": mem,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"{dom}_step (k_step3d)",
+            "achieved": round(roof[dom]["gbs"], 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(roof[dom]["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_us": round(roof[dom]["avg_us"], 1),
+            "algorithmic_bytes_per_launch": roof[dom]["bytes"],
+            "other": {k: {"avg_launch_us": round(v["avg_us"], 1),
+                          "achieved_GBs": round(v["gbs"], 1)}
+                      for k, v in roof.items() if k != dom},
+        },
+        "plain_per_shot": ({"seconds": round(res["plain"], 3),
+                            "Gpt_updates_per_s":
+                                round(pair / res["plain"] / 1e9, 3)}
+                           if "plain" in res else None),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_autograd(args, P, synth, torch):
+    """Differentiation form on the 512 x 1024 model: one forward + backward
+    of 0.5 ||A m - d||^2 through BornFn over an 8-shot window, background
+    checkpointed every ceil(sqrt(nt)) steps vs stored for every step; device
+    memory and recompute cost, and the finite-difference check along 4
+    smoothed seeded directions."""
+    from scipy.ndimage import gaussian_filter
+
+    from paper_1801_00819_amd.autograd import misfit
+    w = synth.config1()
+    nt, nrec = w.nt, w.shots[0].nrec
+    vel = w.vel.astype(np.float32)
+    mt = torch.from_numpy(w.m_true.astype(np.float32)).cuda()
+    res = {}
+    for ck, name in ((-1, "checkpointed"), (0, "stored")):
+        ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt, nrec, 8, w.h, w.dt, 1.0,
+                          vel, device=True, ckpt_interval=ck)
+        for i in w.windows()[0]:
+            s = w.shots[i]
+            ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+        ctx.set_tile(*DEFAULT_TILE)
+        d = ctx.apply_born(mt)
+        m = (0.5 * mt).requires_grad_(True)
+        misfit(m, d, ctx).backward()  # warm-up: graphs
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m.grad = None
+        loss = misfit(m, d, ctx)
+        loss.backward()
+        torch.cuda.synchronize()
+        res[name] = dict(seconds=round(time.perf_counter() - t, 4),
+                         device_bytes=ctx.memory_bytes())
+        if ck == -1:
+            g = m.grad.double()
+            m0 = (0.5 * mt).detach()
+            fds, ans = [], []
+            for k in range(4):
+                p = gaussian_filter(synth.gaussian(w.model_shape, 2000 + k)
+                                    [:, 0, :], 4.0)[:, None, :]
+                p = torch.from_numpy(np.ascontiguousarray(p)).cuda()
+                p *= torch.linalg.vector_norm(m0.double()) / \
+                    torch.linalg.vector_norm(p)
+                mp = (m0.double() + 1e-3 * p).float()
+                mm = (m0.double() - 1e-3 * p).float()
+                pe = (mp.double() - mm.double()) / 2e-3
+                with torch.no_grad():
+                    fds.append(float((misfit(mp, d, ctx) - misfit(mm, d, ctx))
+                                     / 2e-3))
+                ans.append(float(torch.sum(g * pe)))
+            fds, ans = np.array(fds), np.array(ans)
+            res[name]["fd_rel_l2"] = float(np.linalg.norm(fds - ans) /
+                                           np.linalg.norm(ans))
+        ctx.close()
+        log(f"autograd {name}: {res[name]}")
+    pair = 2 * 8 * (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb) * (nt - 1)
+    tc = res["checkpointed"]["seconds"]
+    out = {
+        "metric": "Born+adjoint Gpt-updates/s",
+        "value": round(pair / tc / 1e9, 3),
+        "unit": "Gpt-updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(tc * 1e3, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "faulted2d-512x1024 autograd: BornFn forward "
+                               "+ backward, 8 shots, nt=3000, checkpoints "
+                               "every 55 steps"},
+        "checkpointed": res["checkpointed"],
+        "stored": res["stored"],
+        "recompute_time_ratio": round(tc / res["stored"]["seconds"], 3),
+        "memory_ratio": round(res["checkpointed"]["device_bytes"] /
+                              res["stored"]["device_bytes"], 4),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -112,6 +311,10 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.workload == "3d":
+        return bench_3d(args, P, synth, torch)
+    if args.workload == "autograd":
+        return bench_autograd(args, P, synth, torch)
     w = synth.config1()
     Q, S = w.Q, w.S
     nshots = len(w.shots)

@@ -92,6 +92,7 @@ struct brls_ctx {
   int variant = 0;
   int per_block = 4;
   int resident_grid = 0;
+  int tune_nt = 0;      // > 0 while autotuning: time steps per trial
   int exec = BRLS_EXEC_GRAPH;
   int rows_alloc = 0;
   int64_t fs = 0;      // floats per field buffer
@@ -293,7 +294,7 @@ int ensure_tab(brls_ctx* c) {
 int nt_max_of(const brls_ctx* c, const std::vector<int>& idx) {
   int n = 0;
   for (int i : idx) n = std::max(n, c->slots[i].nt);
-  return n;
+  return c->tune_nt > 0 ? std::min(n, c->tune_nt) : n;
 }
 
 // --- timing ---------------------------------------------------------------
@@ -419,7 +420,7 @@ int enqueue_born(brls_ctx* c, int batched) {
   if ((rc = zero_fields(c))) return rc;
   if (!batched) {
     for (int k = 0; k < nsh; ++k)
-      for (int n = 0; n + 1 < c->slots[c->order[k]].nt; ++n)
+      for (int n = 0; n + 1 < nt_max_of(c, {c->order[k]}); ++n)
         if ((rc = step(c, mode, n, c->tab_dev + k, 1, 1, c->born_in, c->q,
                        nullptr)))
           return rc;
@@ -475,7 +476,7 @@ int enqueue_adjoint(brls_ctx* c, int batched) {
   HIPCHECK(c, launch_fill_f64(c->acc, ngroups * c->mplane, 0.0, c->st));
   if (!batched) {
     for (int k = 0; k < nsh; ++k) {
-      const int nt = c->slots[c->order[k]].nt;
+      const int nt = nt_max_of(c, {c->order[k]});
       rc = c->ckpt_k ? adjoint_segments(c, c->tab_dev + k, 1, 1, nt)
                      : adjoint_steps(c, c->tab_dev + k, 1, 1, nt - 1, 1, 0);
       if (rc) return rc;
@@ -1140,41 +1141,56 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
     return BRLS_OK;
   }
   const int saved_exec = c->exec;
-  c->exec = BRLS_EXEC_BATCHED;
-  hipEvent_t e0, e1;
-  HIPCHECK(c, hipEventCreate(&e0));
-  HIPCHECK(c, hipEventCreate(&e1));
-  float best_ms = 1e30f;
-  int best_v = c->variant, best_pb = c->per_block;
-  int best_rg = c->resident_grid;
-  for (int v = 0; v < variant_count(c); ++v) {
-    for (int trial = 0; trial < 8; ++trial) {
-      int pb = 1 << (trial >> 1);
-      const int rg = trial & 1;
-      if (c->ndim == 3) {  // shots per block fixed by the variant
-        if (trial > 1) break;
-        pb = tile_shape3(v).sb;
-      }
-      if (pb > nsh && pb > 1) break;
-      if ((rc = set_tile_impl(c, v, pb))) return rc;
-      c->resident_grid = rg;
-      HIPCHECK(c, hipEventRecord(e0, c->st));
-      if ((rc = enqueue_born(c, 1)) || (rc = enqueue_adjoint(c, 1))) return rc;
-      HIPCHECK(c, hipEventRecord(e1, c->st));
-      HIPCHECK(c, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best_v = v;
-        best_pb = pb;
-        best_rg = rg;
+  const int saved_v = c->variant, saved_pb = c->per_block,
+            saved_rg = c->resident_grid;
+  int best_v = saved_v, best_pb = saved_pb, best_rg = saved_rg;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto trials = [&]() -> int {
+    HIPCHECK(c, hipEventCreate(&e0));
+    HIPCHECK(c, hipEventCreate(&e1));
+    c->exec = BRLS_EXEC_BATCHED;
+    // trials run a few hundred time steps (the kernels' cost per step does
+    // not depend on the step index)
+    c->tune_nt = 400;
+    float best_ms = 1e30f;
+    for (int v = 0; v < variant_count(c); ++v) {
+      for (int trial = 0; trial < 8; ++trial) {
+        int pb = 1 << (trial >> 1);
+        const int rg = trial & 1;
+        if (c->ndim == 3) {  // shots per block fixed by the variant
+          if (trial > 1) break;
+          pb = tile_shape3(v).sb;
+        }
+        if (pb > nsh && pb > 1) break;
+        int r;
+        if ((r = set_tile_impl(c, v, pb))) return r;
+        c->resident_grid = rg;
+        HIPCHECK(c, hipEventRecord(e0, c->st));
+        if ((r = enqueue_born(c, 1)) || (r = enqueue_adjoint(c, 1))) return r;
+        HIPCHECK(c, hipEventRecord(e1, c->st));
+        HIPCHECK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_v = v;
+          best_pb = pb;
+          best_rg = rg;
+        }
       }
     }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+    return BRLS_OK;
+  };
+  rc = trials();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   c->exec = saved_exec;
+  c->tune_nt = 0;
+  if (rc) {  // restore the previous choice
+    c->resident_grid = saved_rg;
+    (void)set_tile_impl(c, saved_v, saved_pb);
+    return rc;
+  }
   c->resident_grid = best_rg;
   if ((rc = set_tile_impl(c, best_v, best_pb))) return rc;
   if (best) *best = best_v;
