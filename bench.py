@@ -125,7 +125,7 @@ def bench_3d(args, P, synth, torch):
     one 8-shot window, 128 x 128 receivers, nt = 2000, background
     checkpointed every ceil(sqrt(nt)) steps. Times one Born + adjoint pair
     replayed from a graph against the plain per-shot launches."""
-    w = synth.config3()
+    w = synth.layered3d_256x320x320()
     Q = w.Q
     nt, nrec = w.nt, w.shots[0].nrec
     pz, py, px = (w.nz + 2 * w.nb, w.ny + 2 * w.nb, w.nx + 2 * w.nb)
@@ -231,7 +231,7 @@ def bench_autograd(args, P, synth, torch):
     from scipy.ndimage import gaussian_filter
 
     from paper_1801_00819_amd.autograd import misfit
-    w = synth.config1()
+    w = synth.faulted2d_512x1024()
     nt, nrec = w.nt, w.shots[0].nrec
     vel = w.vel.astype(np.float32)
     mt = torch.from_numpy(w.m_true.astype(np.float32)).cuda()
@@ -315,7 +315,7 @@ def main():
         return bench_3d(args, P, synth, torch)
     if args.workload == "autograd":
         return bench_autograd(args, P, synth, torch)
-    w = synth.config1()
+    w = synth.faulted2d_512x1024()
     Q, S = w.Q, w.S
     nshots = len(w.shots)
     nrec = w.shots[0].nrec

@@ -7,13 +7,11 @@ arithmetic (no wavelet, stencil, sponge, propagation or solver); both the GPU
 library and the CPU oracle implement those themselves.
 """
 from .configs import (  # noqa: F401
-    CONFIG_NAMES,
     Workload,
     Shot,
-    workload,
-    config0,
-    config1,
-    config3,
+    layers2d_64x64,
+    faulted2d_512x1024,
+    layered3d_256x320x320,
     noise_like,
     tiny2d,
     tiny3d,

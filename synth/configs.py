@@ -11,8 +11,8 @@ Naming: ``Q`` is the number of shots in a window (the paper's window length)
 and ``S`` is the number of shots added and dropped per slide (the paper's
 rank of update and downdate).
 
-Seeds: ``numpy.random.default_rng(1000 * c + k)`` with c the workload index
-and k = 0 reflectivity, 1 noise, 2 test vectors / finite-difference
+Seeds: ``numpy.random.default_rng(1000 * c + k)`` with c the workload's seed
+group and k = 0 reflectivity, 1 noise, 2 test vectors / finite-difference
 directions, 3 faults and drift.
 """
 from __future__ import annotations
@@ -22,17 +22,14 @@ from typing import List, Optional
 
 import numpy as np
 
-CONFIG_NAMES = {
-    0: "layers2d-64x64",
-    1: "faulted2d-512x1024",
-    2: "faulted2d-512x1024-autograd",
-    3: "layered3d-256x320x320",
-    4: "faulted2d-512x1024-stream",
-}
+# seed groups of the workloads (first factor of the seeds)
+SEED_LAYERS2D_64 = 0
+SEED_FAULTED2D_512 = 1
+SEED_LAYERED3D_256 = 3
 
 
-def rng(config_index: int, stream: int) -> np.random.Generator:
-    return np.random.default_rng(1000 * config_index + stream)
+def rng(seed_group: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(1000 * seed_group + stream)
 
 
 def gaussian(shape, seed: int) -> np.ndarray:
@@ -55,7 +52,7 @@ class Shot:
 @dataclass
 class Workload:
     name: str
-    index: int
+    seed_group: int
     ndim: int
     nz: int
     ny: int
@@ -113,10 +110,10 @@ def _row_receivers(z: int, xs, y: int = 0) -> np.ndarray:
     return out
 
 
-def config0() -> Workload:
+def layers2d_64x64() -> Workload:
     """2-D, 64 x 64, h = 10 m, constant 2000 m/s, three flat reflectors."""
     nz = nx = 64
-    r = rng(0, 0)
+    r = rng(SEED_LAYERS2D_64, 0)
     amps = r.uniform(-0.1, 0.1, size=3)
     m = np.zeros((nz, 1, nx))
     for a, z in zip(amps, (20, 35, 50)):
@@ -125,7 +122,8 @@ def config0() -> Workload:
     rec = _row_receivers(2, range(64))
     shots = [Shot(i, (2, 0, x), rec.copy(), 500, 15.0)
              for i, x in enumerate((8, 24, 40, 56))]
-    return Workload(CONFIG_NAMES[0], 0, 2, nz, 1, nx, 20, 10.0, 1e-3, 500,
+    return Workload("layers2d-64x64", SEED_LAYERS2D_64, 2, nz, 1, nx, 20,
+                    10.0, 1e-3, 500,
                     15.0, vel, m, shots, Q=2, S=1, niter=10, lam_rel=0.01)
 
 
@@ -164,8 +162,8 @@ def faulted_reflectivity(nz: int, nx: int, r_layers, r_faults,
     return m
 
 
-def config1(nz: int = 512, nx: int = 1024, nshots: int = 64,
-            nt: int = 3000) -> Workload:
+def faulted2d_512x1024(nz: int = 512, nx: int = 1024, nshots: int = 64,
+                       nt: int = 3000) -> Workload:
     """2-D, 512 x 1024, h = 5 m, v(z) 1500 -> 4000 m/s with a -300 m/s
     Gaussian anomaly (sigma 200 m), faulted layered reflectivity, 64 shots
     80 m apart, 1024 receivers, nt = 3000, dt = 0.5 ms, 20 Hz."""
@@ -176,25 +174,27 @@ def config1(nz: int = 512, nx: int = 1024, nshots: int = 64,
     sig = 200.0
     vel = 1500.0 + 2500.0 * z / (nz - 1) - 300.0 * np.exp(
         -(((z * h - zc) ** 2 + (x * h - xc) ** 2) / (2 * sig * sig)))
-    m = faulted_reflectivity(nz, nx, rng(1, 0), rng(1, 3))
+    m = faulted_reflectivity(nz, nx, rng(SEED_FAULTED2D_512, 0),
+                             rng(SEED_FAULTED2D_512, 3))
     rec = _row_receivers(2, range(nx))
     spacing = 16
     shots = [Shot(i, (2, 0, 8 + spacing * i), rec.copy(), nt, 20.0)
              for i in range(nshots) if 8 + spacing * i < nx]
-    return Workload(CONFIG_NAMES[1], 1, 2, nz, 1, nx, 40, h, 0.5e-3, nt, 20.0,
+    return Workload("faulted2d-512x1024", SEED_FAULTED2D_512, 2, nz, 1, nx,
+                    40, h, 0.5e-3, nt, 20.0,
                     vel[:, None, :].copy(), m[:, None, :].copy(), shots, Q=8,
                     S=4, niter=20, lam_rel=1e-3)
 
 
-def config3(nz: int = 256, ny: int = 320, nx: int = 320, nt: int = 2000,
-            nrec_side: int = 128) -> Workload:
+def layered3d_256x320x320(nz: int = 256, ny: int = 320, nx: int = 320,
+                          nt: int = 2000, nrec_side: int = 128) -> Workload:
     """3-D, 256 x 320 x 320, h = 10 m, v(z) 1500 -> 3500 m/s, random layered
     reflectivity, 32 shots on an 8 x 4 grid, 128 x 128 receivers,
     nt = 2000, dt = 1 ms, 12 Hz."""
     h = 10.0
     z = np.arange(nz, dtype=np.float64)[:, None, None]
     vel = np.broadcast_to(1500.0 + 2000.0 * z / (nz - 1), (nz, ny, nx)).copy()
-    r = rng(3, 0)
+    r = rng(SEED_LAYERED3D_256, 0)
     nl = 30
     depths = r.uniform(10, nz - 6, size=nl)
     dx = r.uniform(-0.03, 0.03, size=nl)
@@ -221,7 +221,8 @@ def config3(nz: int = 256, ny: int = 320, nx: int = 320, nt: int = 2000,
     for j, sy in enumerate(sys_):
         for i, sx in enumerate(sxs):
             shots.append(Shot(len(shots), (2, sy, sx), rec.copy(), nt, 12.0))
-    return Workload(CONFIG_NAMES[3], 3, 3, nz, ny, nx, 20, h, 1e-3, nt, 12.0,
+    return Workload("layered3d-256x320x320", SEED_LAYERED3D_256, 3, nz, ny,
+                    nx, 20, h, 1e-3, nt, 12.0,
                     vel, m, shots, Q=8, S=4, niter=20, lam_rel=1e-3)
 
 
@@ -266,21 +267,8 @@ def tiny3d(nz: int = 8, ny: int = 8, nx: int = 8, nb: int = 4, nt: int = 80,
                     niter=10, lam_rel=0.01)
 
 
-def workload(index: int, **kw) -> Workload:
-    if index == 0:
-        return config0()
-    if index in (1, 2):
-        w = config1(**kw)
-        if index == 2:
-            w.name, w.index = CONFIG_NAMES[2], 2
-        return w
-    if index == 3:
-        return config3(**kw)
-    raise ValueError(f"no workload {index}")
-
-
-def noise_like(shape, config_index: int) -> np.ndarray:
-    return rng(config_index, 1).standard_normal(shape)
+def noise_like(shape, seed_group: int) -> np.ndarray:
+    return rng(seed_group, 1).standard_normal(shape)
 
 
 def unit_random_like(shape, seed: int, norm: Optional[float] = None):

@@ -104,8 +104,8 @@ def test_3d_full_size_dot_product():
     of cancelling terms."""
     import torch
     from scipy.ndimage import gaussian_filter
-    w = synth.config3()
-    print("config3 full-size dot test", flush=True)
+    w = synth.layered3d_256x320x320()
+    print("256x320x320 full-size dot test", flush=True)
     ctx = open_ctx(w, q_max=2, device=True, ckpt_interval=-1)
     for i in (0, 9):
         s = w.shots[i]

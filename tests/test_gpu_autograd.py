@@ -20,7 +20,7 @@ def test_gradient_matches_oracle_adjoint():
     import torch
 
     from paper_1801_00819_amd.autograd import misfit
-    w = synth.config0()
+    w = synth.layers2d_64x64()
     idx = [0, 1]
     ctx = open_ctx(w, q_max=2, device=True, ckpt_interval=-1)
     _window(ctx, w, idx)
@@ -40,7 +40,7 @@ def test_gradient_matches_oracle_adjoint():
 
 def test_checkpointed_and_cached_backgrounds_agree():
     import torch
-    w = synth.config0()
+    w = synth.layers2d_64x64()
     idx = [0, 1]
     a = open_ctx(w, q_max=2, device=True, ckpt_interval=-1)
     b = open_ctx(w, q_max=2, device=True, ckpt_interval=0)
@@ -59,7 +59,7 @@ def test_checkpointed_and_cached_backgrounds_agree():
 @pytest.fixture(scope="module")
 def big_window():
     import torch
-    w = synth.config1()
+    w = synth.faulted2d_512x1024()
     idx = list(range(8))
     ctx = open_ctx(w, q_max=8, device=True, ckpt_interval=-1)
     _window(ctx, w, idx)

@@ -24,15 +24,15 @@ def P():
 
 
 def _case(name):
-    if name == "config0":
-        w = synth.config0()
+    if name == "layers64":
+        w = synth.layers2d_64x64()
         return w, [0, 1]
     w = ragged2d()
     return w, [0, 1, 2]
 
 
 @pytest.mark.parametrize("ckpt", [0, 7])
-@pytest.mark.parametrize("name", ["config0", "ragged2d"])
+@pytest.mark.parametrize("name", ["layers64", "ragged2d"])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_born_matches_oracle(P, name, mode, ckpt):
     w, idx = _case(name)
@@ -52,7 +52,7 @@ def test_born_matches_oracle(P, name, mode, ckpt):
 
 
 @pytest.mark.parametrize("ckpt", [0, 7, -1])
-@pytest.mark.parametrize("name", ["config0", "ragged2d"])
+@pytest.mark.parametrize("name", ["layers64", "ragged2d"])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_adjoint_matches_oracle(P, name, mode, ckpt):
     w, idx = _case(name)
@@ -111,7 +111,7 @@ def test_gpu_dot_product_identity(P):
 
 def test_device_pointers_match_host(P):
     import torch
-    w, idx = _case("config0")
+    w, idx = _case("layers64")
     hctx = open_ctx(w, q_max=2)
     dctx = open_ctx(w, q_max=2, device=True)
     for i in idx:
@@ -174,11 +174,11 @@ def _gpu_chain(ctx, w, data, niter):
 
 
 @pytest.mark.parametrize("mode,ckpt", [(0, 0), (2, 0), (2, -1)])
-def test_window_chain_matches_oracle_config0(P, mode, ckpt):
+def test_window_chain_matches_oracle_64x64(P, mode, ckpt):
     """Full block-row chain of the 64 x 64 workload: 3 windows of 2 shots
     sliding by 1, 10 CG iterations each, warm-started."""
     import oracle
-    w = synth.config0()
+    w = synth.layers2d_64x64()
     prob, data, lam = _chain_inputs(w, 0)
     ref = oracle.chain(prob, [d.astype(np.float64) for d in data],
                        w.windows(), lam, w.niter)
@@ -191,7 +191,7 @@ def test_window_chain_matches_oracle_config0(P, mode, ckpt):
 
 def test_window_solve_matches_oracle_iterate_norms(P):
     import oracle
-    w = synth.config0()
+    w = synth.layers2d_64x64()
     prob, data, lam = _chain_inputs(w, 0)
     idx = w.windows()[0]
     res = oracle.cgls(prob, idx, [data[i].astype(np.float64) for i in idx],
@@ -214,7 +214,7 @@ def test_rtol_stop_and_warm_start_match_oracle(P):
     stopped images still agree closely. Starting window 1 from window 0's
     image does not need more iterations than starting from zero."""
     import oracle
-    w = synth.config0()
+    w = synth.layers2d_64x64()
     prob, data, lam = _chain_inputs(w, 0)
     d64 = [d.astype(np.float64) for d in data]
     rt = 1e-3
@@ -245,7 +245,7 @@ def test_rtol_stop_and_warm_start_match_oracle(P):
 
 def test_error_paths(P):
     from paper_1801_00819_amd import BrlsError, _lib as L
-    w = synth.config0()
+    w = synth.layers2d_64x64()
     ctx = open_ctx(w, q_max=1)
     st = ctx.solve_window(5)  # empty window
     assert st["iters"] == 0
@@ -274,7 +274,7 @@ def test_error_paths(P):
     assert ctx.solve_window(4)["iters"] == 0
     ctx.close()
     import paper_1801_00819_amd as P_
-    fast = synth.config0()
+    fast = synth.layers2d_64x64()
     fast.vel[:] = 6000.0  # v dt / h = 0.6 > 0.5546
     with pytest.raises(BrlsError) as e:
         open_ctx(fast)
@@ -288,14 +288,14 @@ def test_error_paths(P):
 # ---------------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def big():
-    w = synth.config1()
+    w = synth.faulted2d_512x1024()
     idx = list(range(8))
     return w, idx
 
 
 def test_full_size_born_shot_matches_oracle(P, big):
     w, idx = big
-    print("config1 born, 8-shot window, graph mode", flush=True)
+    print("512x1024 born, 8-shot window, graph mode", flush=True)
     ctx = open_ctx(w, q_max=8)
     for i in idx:
         add_shot(ctx, w, i)
@@ -309,7 +309,7 @@ def test_full_size_born_shot_matches_oracle(P, big):
 
 def test_full_size_adjoint_shot_matches_oracle(P, big):
     w, idx = big
-    print("config1 adjoint, 8-shot window, graph mode", flush=True)
+    print("512x1024 adjoint, 8-shot window, graph mode", flush=True)
     ctx = open_ctx(w, q_max=8)
     for i in idx:
         add_shot(ctx, w, i)

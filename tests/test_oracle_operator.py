@@ -220,9 +220,9 @@ def test_born_is_derivative_of_modelling(orc, ndim):
 # ---------------------------------------------------------------------------
 # Adjoint: dot-product identity and brute-force transpose
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("which", ["config0", "tiny3d"])
+@pytest.mark.parametrize("which", ["layers64", "tiny3d"])
 def test_dot_product_identity(orc, which):
-    w = synth.config0() if which == "config0" else synth.tiny3d()
+    w = synth.layers2d_64x64() if which == "layers64" else synth.tiny3d()
     prob = orc.Problem.from_workload(w)
     idx = list(range(min(2, len(w.shots))))
     m = synth.gaussian(prob.grid.model_shape, 12)
