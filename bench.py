@@ -32,10 +32,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# tile variant and shots per block used without autotuning (and by the
-# counter runs): the autotuner's pick on this workload
-DEFAULT_TILE = (0, 2)
-DEFAULT_TILE3 = 1
+# launch choice used unless --autotune is given (and by the counter runs):
+# tile variant, Born shots per block and grid shape, adjoint shots per block
+# and grid shape -- the fastest in a sweep of all choices on this workload
+DEFAULT_TUNING = (0, 2, 1, 4, 0)
+DEFAULT_TILE3 = 0
 
 
 def parse():
@@ -46,7 +47,9 @@ def parse():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch choice by timing (else the "
+                         "built-in default)")
     ap.add_argument("--cpu-sample-nt", type=int, default=800)
     ap.add_argument("--only-steps", action="store_true",
                     help="time the steps only (for profiler runs)")
@@ -97,7 +100,7 @@ def ops_only(P, w, vel, m_true):
     for i in w.windows()[0]:
         s = w.shots[i]
         ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
-    ctx.set_tile(*DEFAULT_TILE)
+    ctx.set_tuning(*DEFAULT_TUNING)
     ctx.set_exec(P.BRLS_EXEC_BATCHED)
     ctx.apply_adjoint(ctx.apply_born(m_true))
     torch.cuda.synchronize()
@@ -138,15 +141,14 @@ def bench_3d(args, P, synth, torch):
         s = w.shots[i]
         ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
     t = time.perf_counter()
-    if args.no_autotune:
+    if args.autotune:
+        ctx.autotune()
+    else:
         ctx.set_tile(DEFAULT_TILE3)
         ctx.apply_born(m)  # builds the background checkpoints
-    else:
-        ctx.autotune()
     torch.cuda.synchronize()
     log(f"3d: checkpoints + tuning {time.perf_counter() - t:.1f}s, tile "
-        f"{ctx.get_tile()} {P.tile3_variants()[ctx.get_tile()[0]]} "
-        f"resident grid {ctx.get_resident_grid()}")
+        f"{ctx.get_tuning()} {P.tile3_variants()[ctx.get_tile()[0]]}")
     res = {}
     modes = [(P.BRLS_EXEC_GRAPH, "graph")]
     if not args.no_plain:
@@ -242,7 +244,7 @@ def bench_autograd(args, P, synth, torch):
         for i in w.windows()[0]:
             s = w.shots[i]
             ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
-        ctx.set_tile(*DEFAULT_TILE)
+        ctx.set_tuning(*DEFAULT_TUNING)
         d = ctx.apply_born(mt)
         m = (0.5 * mt).requires_grad_(True)
         misfit(m, d, ctx).backward()  # warm-up: graphs
@@ -389,16 +391,17 @@ def main():
         ctx.image(image)
         return st
 
-    ctx.set_tile(*DEFAULT_TILE)
-    if not args.no_autotune and not args.only_steps:
+    ctx.set_tuning(*DEFAULT_TUNING)
+    if args.autotune:
         for i in win0:
             s = w.shots[i]
             ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
             held.append(i)
         t = time.perf_counter()
         best = ctx.autotune()
-        log(f"autotune: variant {ctx.get_tile()} "
-            f"({P.tile_variants()[best]}) in {time.perf_counter() - t:.1f}s")
+        log(f"autotune: {ctx.get_tuning()} ({P.tile_variants()[best]}) in "
+            f"{time.perf_counter() - t:.1f}s")
+    tuning = ctx.get_tuning()
 
     nwin = args.warmup + args.steps
     if nwin > len(windows):
@@ -442,7 +445,7 @@ def main():
             "slide": S,
             "cg_iters": args.iters,
             "exec": "graph",
-            "tile_variant": list(ctx.get_tile()),
+            "launch": tuning,
         },
         "s_per_window": round(elapsed / args.steps, 4),
         "cg_scalars": "f64",
@@ -459,12 +462,13 @@ def main():
     ctx.apply_adjoint(dwin)
     ks = ctx.kernel_stats()
     ctx.kernel_timing(False)
-    var, pb = ctx.get_tile()
-    ngroups = (Q + pb - 1) // pb
+    var = tuning["variant"]
     roof = {}
     for kind, name in (("born", "born_step"), ("adjoint", "adjoint_step")):
         n, ms = ks[name]
         avg_s = ms / n / 1e3
+        pb = tuning["born_per_block" if kind == "born" else "adj_per_block"]
+        ngroups = (Q + pb - 1) // pb
         byt = algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec)
         roof[kind] = dict(avg_us=avg_s * 1e6, bytes=byt,
                           gbs=byt / avg_s / 1e9)
@@ -472,8 +476,9 @@ def main():
     r = roof[dom]
     out["roofline"] = {
         "bound": "hbm",
-        "kernel": f"{dom}_step (k_step2d, {P.tile_variants()[var]}, "
-                  f"{pb} shots/block)",
+        "kernel": f"{dom}_step (k_step2d, tile {P.tile_variants()[var]}, "
+                  f"{tuning['born_per_block' if dom == 'born' else 'adj_per_block']}"
+                  f" shots/block)",
         "achieved": round(r["gbs"], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",

@@ -189,7 +189,8 @@ int brls_tile3_info(int32_t variant, int32_t* tx, int32_t* ty,
 int brls_tile_info(int32_t variant, int32_t* tx, int32_t* tz,
                    int32_t* thread_rows, int32_t* pipelined);
 
-/* Shots one block handles in turn in batched modes (default 4). */
+/* Shots one block handles in turn in batched modes (default 4), for both
+ * operators. */
 int brls_set_shots_per_block(brls_ctx* ctx, int32_t per_block);
 int brls_get_tile(const brls_ctx* ctx, int32_t* variant, int32_t* per_block);
 
@@ -199,10 +200,20 @@ int brls_get_tile(const brls_ctx* ctx, int32_t* variant, int32_t* per_block);
 int brls_set_resident_grid(brls_ctx* ctx, int32_t enable);
 int brls_get_resident_grid(const brls_ctx* ctx, int32_t* enable);
 
+/* Set / read the launch choice: tile variant, and shots per block and grid
+ * shape (0 one block per work item, 1 resident grid) of the Born (and
+ * background) launches and of the adjoint launches. 3-D variants fix the
+ * shots per block. */
+int brls_set_tuning(brls_ctx* ctx, int32_t variant, int32_t born_pb,
+                    int32_t born_grid, int32_t adj_pb, int32_t adj_grid);
+int brls_get_tuning(const brls_ctx* ctx, int32_t* variant, int32_t* born_pb,
+                    int32_t* born_grid, int32_t* adj_pb, int32_t* adj_grid);
+
 /* Time every tile variant, shots-per-block choice and grid shape on the
  * current window
- * (one Born and one adjoint application each, results discarded) and keep
- * the fastest. Returns the chosen variant in *best. */
+ * (Born and adjoint applications of 400 time steps, results discarded)
+ * and keep the fastest, shots per block and grid shape chosen per operator.
+ * Returns the chosen variant in *best. */
 int brls_autotune(brls_ctx* ctx, int32_t* best);
 
 /* Per-kernel timing with HIP events around every launch (adds small gaps

@@ -208,6 +208,26 @@ class Context:
 
     get_resident_grid = brls_get_resident_grid
 
+    def brls_set_tuning(self, variant: int, born_per_block: int,
+                        born_resident_grid: int, adj_per_block: int,
+                        adj_resident_grid: int):
+        self._check(L.lib().brls_set_tuning(
+            self._h, int(variant), int(born_per_block),
+            int(born_resident_grid), int(adj_per_block),
+            int(adj_resident_grid)))
+
+    set_tuning = brls_set_tuning
+
+    def brls_get_tuning(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(5)]
+        self._check(L.lib().brls_get_tuning(self._h,
+                                            *[ctypes.byref(x) for x in v]))
+        return dict(variant=v[0].value, born_per_block=v[1].value,
+                    born_resident_grid=v[2].value, adj_per_block=v[3].value,
+                    adj_resident_grid=v[4].value)
+
+    get_tuning = brls_get_tuning
+
     def brls_autotune(self) -> int:
         best = ctypes.c_int32()
         self._check(L.lib().brls_autotune(self._h, ctypes.byref(best)))

@@ -100,6 +100,8 @@ SIGNATURES = [
                              ctypes.POINTER(_I32)]),
     ("brls_set_resident_grid", _I32, [_VP, _I32]),
     ("brls_get_resident_grid", _I32, [_VP, ctypes.POINTER(_I32)]),
+    ("brls_set_tuning", _I32, [_VP, _I32, _I32, _I32, _I32, _I32]),
+    ("brls_get_tuning", _I32, [_VP] + [ctypes.POINTER(_I32)] * 5),
     ("brls_autotune", _I32, [_VP, ctypes.POINTER(_I32)]),
     ("brls_kernel_timing", _I32, [_VP, _I32]),
     ("brls_kernel_stats", _I32, [_VP, ctypes.POINTER(brls_kstat), _I32,

@@ -90,8 +90,10 @@ struct brls_ctx {
   Geo2D geo{};
   Geo3D geo3{};
   int variant = 0;
-  int per_block = 4;
+  int per_block = 4;      // Born and background launches
   int resident_grid = 0;
+  int adj_per_block = 4;  // adjoint launches
+  int adj_resident_grid = 0;
   int tune_nt = 0;      // > 0 while autotuning: time steps per trial
   int exec = BRLS_EXEC_GRAPH;
   int rows_alloc = 0;
@@ -318,7 +320,7 @@ StepArgs base_args(const brls_ctx* c) {
   a.g = c->geo;
   a.g3 = c->geo3;
   a.wp = c->wp;
-  a.resident_grid = c->resident_grid;
+  a.resident_grid = c->resident_grid;  // step() overrides for the adjoint
   return a;
 }
 
@@ -333,6 +335,7 @@ int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
   a.nshots = nshots;
   a.per_block = per_block;
   a.ngroups = (nshots + per_block - 1) / per_block;
+  if (mode == kAdjoint) a.resident_grid = c->adj_resident_grid;
   a.n = n;
   a.pm = pm;
   a.dat = dat;
@@ -469,7 +472,7 @@ int adjoint_segments(brls_ctx* c, const ShotDev* tab, int nsh, int pb,
 int enqueue_adjoint(brls_ctx* c, int batched) {
   const int nsh = (int)c->order.size();
   const int ntm = nt_max_of(c, c->order);
-  const int pb = batched ? std::min(c->per_block, nsh) : 1;
+  const int pb = batched ? std::min(c->adj_per_block, nsh) : 1;
   const int ngroups = batched ? (nsh + pb - 1) / pb : 1;
   int rc;
   if ((rc = zero_fields(c))) return rc;
@@ -503,8 +506,11 @@ int run_op(brls_ctx* c, int op) {
     return op == kBorn ? enqueue_born(c, c->exec == BRLS_EXEC_BATCHED)
                        : enqueue_adjoint(c, c->exec == BRLS_EXEC_BATCHED);
   const int nsh = (int)c->order.size();
-  const GraphKey key(op, nsh, std::min(c->per_block, nsh), c->variant,
-                     nt_max_of(c, c->order), c->resident_grid);
+  const bool adj = op == kAdjoint;
+  const GraphKey key(op, nsh,
+                     std::min(adj ? c->adj_per_block : c->per_block, nsh),
+                     c->variant, nt_max_of(c, c->order),
+                     adj ? c->adj_resident_grid : c->resident_grid);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     const bool was_timing = c->timing;
@@ -690,7 +696,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
     c->ntiles_max = std::max(c->ntiles_max, receiver_bins(c));
   }
   set_variant_geo(c, 0);
-  if (g.ndim == 3) c->per_block = tile_shape3(0).sb;
+  if (g.ndim == 3) c->per_block = c->adj_per_block = tile_shape3(0).sb;
   c->mplane = mpts;
   if (g.ckpt_interval < 0)
     c->ckpt_k = std::max(1, (int)std::ceil(std::sqrt((double)g.nt_max)));
@@ -1092,16 +1098,19 @@ int brls_tile_info(int32_t v, int32_t* tx, int32_t* tz, int32_t* rows,
   return BRLS_OK;
 }
 
-static int set_tile_impl(brls_ctx* c, int v, int per_block) {
+static int set_tile_impl(brls_ctx* c, int v, int per_block,
+                         int adj_per_block) {
   if (v < 0 || v >= variant_count(c))
     return fail(c, BRLS_EINVAL, "tile variant %d out of range", v);
   if (per_block < 1) per_block = 1;
+  if (adj_per_block < 1) adj_per_block = 1;
   // 3-D kernels advance a fixed number of shots per block together
-  if (c->ndim == 3) per_block = tile_shape3(v).sb;
+  if (c->ndim == 3) per_block = adj_per_block = tile_shape3(v).sb;
   HIPCHECK(c, hipStreamSynchronize(c->st));
   const bool changed = v != c->variant;
   set_variant_geo(c, v);
   c->per_block = per_block;
+  c->adj_per_block = adj_per_block;
   if (changed) {
     drop_graphs(c);
     for (auto& sl : c->slots)
@@ -1115,7 +1124,8 @@ static int set_tile_impl(brls_ctx* c, int v, int per_block) {
 
 int brls_set_tile(brls_ctx* c, int32_t variant) {
   if (!c) return BRLS_EINVAL;
-  return set_tile_impl(c, variant < 0 ? 0 : variant, c->per_block);
+  return set_tile_impl(c, variant < 0 ? 0 : variant, c->per_block,
+                       c->adj_per_block);
 }
 
 int brls_set_shots_per_block(brls_ctx* c, int32_t per_block) {
@@ -1125,7 +1135,7 @@ int brls_set_shots_per_block(brls_ctx* c, int32_t per_block) {
     return fail(c, BRLS_EINVAL,
                 "3-D tile variant %d advances %d shots per block", c->variant,
                 tile_shape3(c->variant).sb);
-  c->per_block = per_block;
+  c->per_block = c->adj_per_block = per_block;
   return BRLS_OK;
 }
 
@@ -1142,9 +1152,21 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
   }
   const int saved_exec = c->exec;
   const int saved_v = c->variant, saved_pb = c->per_block,
-            saved_rg = c->resident_grid;
-  int best_v = saved_v, best_pb = saved_pb, best_rg = saved_rg;
+            saved_apb = c->adj_per_block, saved_rg = c->resident_grid,
+            saved_arg = c->adj_resident_grid;
+  int best_v = saved_v, best_pb = saved_pb, best_apb = saved_apb,
+      best_rg = saved_rg, best_arg = saved_arg;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // time one operator application with the current settings
+  auto timed = [&](int op, float* ms) -> int {
+    HIPCHECK(c, hipEventRecord(e0, c->st));
+    const int r = op == kBorn ? enqueue_born(c, 1) : enqueue_adjoint(c, 1);
+    if (r) return r;
+    HIPCHECK(c, hipEventRecord(e1, c->st));
+    HIPCHECK(c, hipEventSynchronize(e1));
+    HIPCHECK(c, hipEventElapsedTime(ms, e0, e1));
+    return BRLS_OK;
+  };
   auto trials = [&]() -> int {
     HIPCHECK(c, hipEventCreate(&e0));
     HIPCHECK(c, hipEventCreate(&e1));
@@ -1152,8 +1174,12 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
     // trials run a few hundred time steps (the kernels' cost per step does
     // not depend on the step index)
     c->tune_nt = 400;
-    float best_ms = 1e30f;
+    float best_total = 1e30f;
     for (int v = 0; v < variant_count(c); ++v) {
+      // the tile shape fixes the receiver lists; shots per block and grid
+      // shape are chosen per operator
+      float bt[2] = {1e30f, 1e30f};
+      int bpb[2] = {1, 1}, brg[2] = {0, 0};
       for (int trial = 0; trial < 8; ++trial) {
         int pb = 1 << (trial >> 1);
         const int rg = trial & 1;
@@ -1163,20 +1189,25 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
         }
         if (pb > nsh && pb > 1) break;
         int r;
-        if ((r = set_tile_impl(c, v, pb))) return r;
-        c->resident_grid = rg;
-        HIPCHECK(c, hipEventRecord(e0, c->st));
-        if ((r = enqueue_born(c, 1)) || (r = enqueue_adjoint(c, 1))) return r;
-        HIPCHECK(c, hipEventRecord(e1, c->st));
-        HIPCHECK(c, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-          best_ms = ms;
-          best_v = v;
-          best_pb = pb;
-          best_rg = rg;
+        if ((r = set_tile_impl(c, v, pb, pb))) return r;
+        c->resident_grid = c->adj_resident_grid = rg;
+        for (int k = 0; k < 2; ++k) {
+          float ms = 0.f;
+          if ((r = timed(k == 0 ? kBorn : kAdjoint, &ms))) return r;
+          if (ms < bt[k]) {
+            bt[k] = ms;
+            bpb[k] = pb;
+            brg[k] = rg;
+          }
         }
+      }
+      if (bt[0] + bt[1] < best_total) {
+        best_total = bt[0] + bt[1];
+        best_v = v;
+        best_pb = bpb[0];
+        best_apb = bpb[1];
+        best_rg = brg[0];
+        best_arg = brg[1];
       }
     }
     return BRLS_OK;
@@ -1188,12 +1219,37 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
   c->tune_nt = 0;
   if (rc) {  // restore the previous choice
     c->resident_grid = saved_rg;
-    (void)set_tile_impl(c, saved_v, saved_pb);
+    c->adj_resident_grid = saved_arg;
+    (void)set_tile_impl(c, saved_v, saved_pb, saved_apb);
     return rc;
   }
   c->resident_grid = best_rg;
-  if ((rc = set_tile_impl(c, best_v, best_pb))) return rc;
+  c->adj_resident_grid = best_arg;
+  if ((rc = set_tile_impl(c, best_v, best_pb, best_apb))) return rc;
   if (best) *best = best_v;
+  return BRLS_OK;
+}
+
+int brls_set_tuning(brls_ctx* c, int32_t variant, int32_t born_pb,
+                    int32_t born_grid, int32_t adj_pb, int32_t adj_grid) {
+  if (!c) return BRLS_EINVAL;
+  if (born_pb < 1 || adj_pb < 1)
+    return fail(c, BRLS_EINVAL, "shots per block must be >= 1");
+  const int rc = set_tile_impl(c, variant, born_pb, adj_pb);
+  if (rc) return rc;
+  c->resident_grid = born_grid != 0;
+  c->adj_resident_grid = adj_grid != 0;
+  return BRLS_OK;
+}
+
+int brls_get_tuning(const brls_ctx* c, int32_t* variant, int32_t* born_pb,
+                    int32_t* born_grid, int32_t* adj_pb, int32_t* adj_grid) {
+  if (!c) return BRLS_EINVAL;
+  if (variant) *variant = c->variant;
+  if (born_pb) *born_pb = c->per_block;
+  if (born_grid) *born_grid = c->resident_grid;
+  if (adj_pb) *adj_pb = c->adj_per_block;
+  if (adj_grid) *adj_grid = c->adj_resident_grid;
   return BRLS_OK;
 }
 
@@ -1206,7 +1262,7 @@ int brls_get_tile(const brls_ctx* c, int32_t* variant, int32_t* per_block) {
 
 int brls_set_resident_grid(brls_ctx* c, int32_t enable) {
   if (!c) return BRLS_EINVAL;
-  c->resident_grid = enable != 0;
+  c->resident_grid = c->adj_resident_grid = enable != 0;
   return BRLS_OK;
 }
 

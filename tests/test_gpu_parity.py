@@ -76,10 +76,10 @@ def test_every_tile_shape_matches_oracle(P, variant, ckpt):
     w, idx = _case("ragged2d")
     print(f"tile variant {variant} ckpt={ckpt}", flush=True)
     ctx = open_ctx(w, q_max=3, ckpt_interval=ckpt)
-    for pb in (1, 2, 3):
-        ctx.set_tile(variant, pb)
-        for i in idx:
-            if pb == 1:
+    for pb, apb, rg in ((1, 1, 0), (2, 3, 1), (3, 2, 0), (2, 2, 1)):
+        ctx.set_tuning(variant, pb, rg, apb, 1 - rg)
+        if pb == 1:
+            for i in idx:
                 add_shot(ctx, w, i)
         prob = oracle_problem(w)
         m32 = f32(w.m_true)
