@@ -38,6 +38,39 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 DEFAULT_TUNING = (0, 2, 1, 4, 0)
 DEFAULT_TILE3 = 0
 
+# HBM bytes per launch of the 2-D step kernel under DEFAULT_TUNING, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --ops-only`, scaled
+# by the same counters on a 512 MiB copy (fetch x 2.000, write x 1.000).
+# Valid only for the kernel source they were taken on: reported as null
+# once stencil2d.hip or layout.h hash differently.
+TRAFFIC_2D = {
+    "sources_sha256_16": "3e1cb3211978a349",
+    "born": 2 * 40019.4 * 1024 + 40880.0 * 1024,
+    "adjoint": 2 * 38262.7 * 1024 + 49040.0 * 1024,
+}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("stencil2d.hip", "layout.h"):
+        with open(os.path.join(ROOT, "paper_1801_00819_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind, tuning):
+    """Counter-measured HBM bytes per launch, or None when the kernel or
+    the launch choice differs from the one the counters were taken on."""
+    t = (tuning["variant"], tuning["born_per_block"],
+         tuning["born_resident_grid"], tuning["adj_per_block"],
+         tuning["adj_resident_grid"])
+    if t != DEFAULT_TUNING or \
+            kernel_sources_hash() != TRAFFIC_2D["sources_sha256_16"]:
+        return None
+    return int(TRAFFIC_2D[kind])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -50,7 +83,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch choice by timing (else the "
                          "built-in default)")
-    ap.add_argument("--cpu-sample-nt", type=int, default=800)
+    ap.add_argument("--cpu-sample-nt", type=int, default=3000)
+    ap.add_argument("--cpu-sample-shots", type=int, default=2)
     ap.add_argument("--only-steps", action="store_true",
                     help="time the steps only (for profiler runs)")
     ap.add_argument("--workload", default="2d",
@@ -483,7 +517,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom, tuning),
         "avg_launch_us": round(r["avg_us"], 2),
         "algorithmic_bytes_per_launch": r["bytes"],
         "other": {k: {"avg_launch_us": round(v["avg_us"], 2),
@@ -516,24 +550,25 @@ def main():
     # ---- CPU baseline: the FP64 oracle on a bounded sample -------------
     if not args.no_cpu_baseline:
         import oracle
-        ns = args.cpu_sample_nt
-        s0 = w.shots[0]
-        shot = synth.Shot(0, s0.src, s0.rec, ns, s0.f0)
+        ns, nsh = args.cpu_sample_nt, args.cpu_sample_shots
+        shots = [synth.Shot(i, w.shots[i].src, w.shots[i].rec, ns,
+                            w.shots[i].f0) for i in range(nsh)]
         grid = oracle.Grid(2, w.nz, 1, w.nx, w.nb, w.h, w.dt)
-        prob = oracle.Problem(grid, vel.astype(np.float64), [shot])
+        prob = oracle.Problem(grid, vel.astype(np.float64), shots)
         m64 = w.m_true.astype(np.float64)
         t = time.perf_counter()
-        d = prob.born_shot(0, m64)
-        prob.adjoint_shot(0, d)
+        for i in range(nsh):
+            d = prob.born_shot(i, m64)
+            prob.adjoint_shot(i, d)
         tc = time.perf_counter() - t
         cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
         out["cpu_baseline"] = {
-            "value": round(2 * npad * (ns - 1) / tc / 1e9, 4),
+            "value": round(2 * nsh * npad * (ns - 1) / tc / 1e9, 4),
             "unit": "Gpt-updates/s",
             "cores": cores,
             "kind": "oracle",
-            "sample": f"1 shot, nt={ns} (of 3000), one Born + one adjoint "
-                      f"application, FP64, {tc:.1f}s",
+            "sample": f"{nsh} shots, nt={ns} (of {nt}), one Born + one "
+                      f"adjoint application each, FP64, {tc:.1f}s",
         }
         log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
