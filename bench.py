@@ -35,7 +35,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # launch choice used unless --autotune is given (and by the counter runs):
 # tile variant, Born shots per block and grid shape, adjoint shots per block
 # and grid shape -- the fastest in a sweep of all choices on this workload
-DEFAULT_TUNING = (0, 2, 1, 4, 0)
+# (z-marching wavefronts over 8-row chunks; adjoint work items in launch
+# order)
+DEFAULT_TUNING = (16, 1, 0, 4, 2)
 DEFAULT_TILE3 = 0
 
 # HBM bytes per launch of the 2-D step kernel under DEFAULT_TUNING, from

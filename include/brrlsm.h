@@ -177,8 +177,12 @@ int brls_set_exec(brls_ctx* ctx, int32_t mode);
 
 /* Tile shape of the stencil kernels: index into the compiled variants
  * (brls_tile_count); -1 restores the default. brls_tile_info reports a
- * variant's tile width tx, height tz, thread rows, and whether a block
- * issues the next shot's loads before computing the current one. */
+ * variant's tile width tx, height tz, thread rows, and its kind in
+ * `pipelined`: 0 = a block stages the tile (with its 4-cell halo) in LDS and
+ * runs its shots in turn; 1 = the same, the next shot's loads issued before
+ * the current shot is computed; 2 = z-marching wavefronts: each wavefront
+ * walks a tx-column strip down a tz-row chunk with the z-stencil in
+ * registers and the x-stencil from neighbouring lanes (thread rows 1). */
 int brls_set_tile(brls_ctx* ctx, int32_t variant);
 int brls_tile_count(int32_t* n);
 /* 3-D variants: XY tile tx x ty and the shots a block advances together
@@ -201,9 +205,11 @@ int brls_set_resident_grid(brls_ctx* ctx, int32_t enable);
 int brls_get_resident_grid(const brls_ctx* ctx, int32_t* enable);
 
 /* Set / read the launch choice: tile variant, and shots per block and grid
- * shape (0 one block per work item, 1 resident grid) of the Born (and
- * background) launches and of the adjoint launches. 3-D variants fix the
- * shots per block. */
+ * shape of the Born (and background) launches and of the adjoint launches.
+ * Grid shape bits: bit 0 = resident grid (as brls_set_resident_grid);
+ * bit 1 (2-D only) = work items dealt to blocks in launch order instead of
+ * in 8 contiguous ranges, one per XCD. 3-D variants fix the shots per
+ * block. */
 int brls_set_tuning(brls_ctx* ctx, int32_t variant, int32_t born_pb,
                     int32_t born_grid, int32_t adj_pb, int32_t adj_grid);
 int brls_get_tuning(const brls_ctx* ctx, int32_t* variant, int32_t* born_pb,

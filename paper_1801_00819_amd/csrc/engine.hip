@@ -238,6 +238,11 @@ int build_receiver_tiles(brls_ctx* c, Slot& sl) {
     e.y = j;
     ent[fillp[binof[j]]++] = e;
   }
+  // each bin in local-index order (2-D: by row, then column), which the
+  // z-marching kernels rely on
+  for (int b = 0; b < nbins; ++b)
+    std::stable_sort(ent.begin() + cnt[b], ent.begin() + cnt[b + 1],
+                     [](const int2& p, const int2& q) { return p.x < q.x; });
   HIPCHECK(c, hipMemcpyAsync(sl.rptr, cnt.data(), sizeof(int) * cnt.size(),
                              hipMemcpyHostToDevice, c->st));
   HIPCHECK(c, hipMemcpyAsync(sl.rent, ent.data(), sizeof(int2) * sl.nrec,
@@ -1180,9 +1185,11 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
       // shape are chosen per operator
       float bt[2] = {1e30f, 1e30f};
       int bpb[2] = {1, 1}, brg[2] = {0, 0};
-      for (int trial = 0; trial < 8; ++trial) {
-        int pb = 1 << (trial >> 1);
-        const int rg = trial & 1;
+      // shots per block 1, 2, 4, 8 x grid shape: one block per item,
+      // resident grid, items in launch order (2-D only)
+      for (int trial = 0; trial < 12; ++trial) {
+        int pb = 1 << (trial / 3);
+        const int rg = trial % 3;
         if (c->ndim == 3) {  // shots per block fixed by the variant
           if (trial > 1) break;
           pb = tile_shape3(v).sb;
@@ -1237,8 +1244,8 @@ int brls_set_tuning(brls_ctx* c, int32_t variant, int32_t born_pb,
     return fail(c, BRLS_EINVAL, "shots per block must be >= 1");
   const int rc = set_tile_impl(c, variant, born_pb, adj_pb);
   if (rc) return rc;
-  c->resident_grid = born_grid != 0;
-  c->adj_resident_grid = adj_grid != 0;
+  c->resident_grid = born_grid & 3;
+  c->adj_resident_grid = adj_grid & 3;
   return BRLS_OK;
 }
 

@@ -9,7 +9,9 @@ namespace brls {
 
 struct TileShape {
   int tx, tz, ntz;  // tile width (x), tile height (z), thread rows
-  int pipe;         // next shot's loads issued before computing the current
+                    // (z-marching: rows of loads in flight ahead)
+  int pipe;         // 0: staged tile; 1: staged, next shot's loads issued
+                    // before computing the current; 2: z-marching
 };
 
 int tile_shape_count();
@@ -26,6 +28,15 @@ hipError_t launch_step3d(int variant, int mode, const StepArgs& a,
 hipError_t launch_adj_finalize3(const double* acc, int ngroups,
                                 const Geo3D& g, const float* wp, float* out,
                                 hipStream_t st);
+
+// Blocks of `kernel` (launched with `threads` per block) that fit on the
+// current device at once.
+int resident_blocks(const void* kernel, int threads);
+
+// z-marching 2-D step over chunks of cz rows (8, 16 or 32), the loads of
+// `ahead` rows (2 or 4) in flight ahead of the row computed.
+hipError_t launch_march2d(int cz, int ahead, int mode, const StepArgs& a,
+                          hipStream_t st);
 
 // One time step for all shots of `a` (mode: StepMode).
 hipError_t launch_step2d(int variant, int mode, const StepArgs& a,

@@ -97,8 +97,10 @@ struct StepArgs {
                        // output level k (adjoint)
   int d2_n0;           // time level of stored frame 0
   int write_d2;        // background: store frames
-  int resident_grid;   // launch only as many blocks as fit at once (each
-                       // loops over work items); else one block per item
+  int resident_grid;   // bit 0: launch only as many blocks as fit at once
+                       // (each loops over work items), else one block per
+                       // item; bit 1: deal work items to blocks in launch
+                       // order, else in 8 contiguous per-XCD ranges
   const float* wp;     // W' = v^2 dt^2 / h^2, storage layout
   const float* pm;     // Born: model perturbation [nz][nx]
   float* dat;          // Born: output data base; adjoint: input residual base

@@ -28,70 +28,15 @@
 // written with non-temporal hints (it is touched once per step).
 #include <hip/hip_runtime.h>
 
+#include "devutil.h"
 #include "kernels.h"
 #include "layout.h"
-
-#define GLOBAL __attribute__((address_space(1)))
 
 namespace brls {
 
 namespace {
 
-typedef GLOBAL float gfloat;
-typedef const GLOBAL float cgfloat;
-
-__device__ __forceinline__ gfloat* G(float* p) { return (gfloat*)p; }
-__device__ __forceinline__ cgfloat* G(const float* p) { return (cgfloat*)p; }
-
-// Every value of a shot's table entry is uniform across the block; moving
-// them to scalar registers lets global accesses use a scalar base plus a
-// 32-bit vector offset instead of 64-bit vector address arithmetic.
-__device__ __forceinline__ uint32_t uni(uint32_t v) {
-  return __builtin_amdgcn_readfirstlane(v);
-}
-__device__ __forceinline__ int uni(int v) {
-  return (int)__builtin_amdgcn_readfirstlane((uint32_t)v);
-}
-__device__ __forceinline__ uint64_t uni(uint64_t v) {
-  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
-}
-template <class T>
-__device__ __forceinline__ T* uni(T* p) {
-  return (T*)(uintptr_t)uni((uint64_t)(uintptr_t)p);
-}
-__device__ __forceinline__ ShotDev shot(const ShotDev* tab, int s) {
-  ShotDev d = tab[s];
-  for (int k = 0; k < 3; ++k) {
-    d.f[k] = uni(d.f[k]);
-    d.b[k] = uni(d.b[k]);
-  }
-  d.d2 = uni(d.d2);
-  d.ck = uni(d.ck);
-  d.rptr = uni(d.rptr);
-  d.rent = uni(d.rent);
-  d.rsidx = uni(d.rsidx);
-  d.wav = uni(d.wav);
-  d.dat_off = (int64_t)uni((uint64_t)d.dat_off);
-  d.nt = uni(d.nt);
-  d.nrec = uni(d.nrec);
-  d.src_z = uni(d.src_z);
-  d.src_x = uni(d.src_x);
-  return d;
-}
-
-// Element i of a global array, the byte offset formed in 32 bits so the
-// access can use a scalar base plus a 32-bit vector offset (every array the
-// kernels index this way is below 2^30 elements).
-__device__ __forceinline__ cgfloat* at(cgfloat* base, uint32_t i) {
-  return (cgfloat*)((const GLOBAL char*)base + (i << 2));
-}
-__device__ __forceinline__ gfloat* at(gfloat* base, uint32_t i) {
-  return (gfloat*)((GLOBAL char*)base + (i << 2));
-}
-
-__device__ __forceinline__ int sponge_depth(int i, int nb, int n) {
-  return i < nb ? nb - i : (i >= nb + n ? i - (nb + n - 1) : 0);
-}
+using namespace dev;
 
 // L u * h^2 at one point on differences, smallest weights first. col: the
 // thread's register column (centre at col[j+4]); rw: the point in LDS.
@@ -364,13 +309,21 @@ __global__ void __launch_bounds__(TX* NTZ) k_step2d(StepArgs a) {
   // per XCD (the hardware deals consecutive block ids to the 8 XCDs in
   // turn; gridDim.x is a multiple of 8), and each block loops over its
   // XCD's range with a stride of the number of blocks placed there.
+  // (Or, with bit 1 of resident_grid, in launch order.)
   const int items = g.ntiles * a.ngroups;
-  const int xcd = blockIdx.x & 7;
-  const int nbx = gridDim.x >> 3;
-  const int q = items >> 3, r = items & 7;
-  const int lo = xcd * q + min(xcd, r);
-  const int hi = lo + q + (xcd < r ? 1 : 0);
-  for (int L = lo + (int)(blockIdx.x >> 3); L < hi; L += nbx) {
+  int first, hi, stride;
+  if (a.resident_grid & 2) {
+    first = blockIdx.x;
+    hi = items;
+    stride = gridDim.x;
+  } else {
+    const int xcd = blockIdx.x & 7;
+    const int q = items >> 3, r = items & 7;
+    first = xcd * q + min(xcd, r) + (int)(blockIdx.x >> 3);
+    hi = xcd * q + min(xcd, r) + q + (xcd < r ? 1 : 0);
+    stride = gridDim.x >> 3;
+  }
+  for (int L = first; L < hi; L += stride) {
     const int t = L % g.ntiles;
     const int grp = L / g.ntiles;
     const int tzi = t / g.ntx;
@@ -439,12 +392,17 @@ __global__ void k_ckpt(const ShotDev* tab, int nshots, int n0, int seg,
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-// Tile shapes the autotuner chooses from: (TX, TZ, thread rows, whether the
-// next shot's loads are issued before the current shot is computed).
+// Tile shapes the autotuner chooses from: (TX, TZ, thread rows, kind) with
+// kind 0 = staged tile, shots in turn; 1 = staged tile, the next shot's
+// loads issued before the current shot is computed; 2 = z-marching
+// wavefronts (march2d.hip: 64-column strips of TZ-row chunks; the third
+// number is then the rows of loads in flight ahead of the row computed).
 static const TileShape kShapes[] = {
     {64, 16, 4, 0}, {64, 32, 4, 0}, {64, 8, 2, 0},  {32, 32, 8, 0},
     {64, 32, 8, 0}, {32, 16, 4, 0}, {64, 16, 4, 1}, {32, 32, 8, 1},
-    {32, 16, 4, 1}, {64, 32, 8, 1}, {64, 8, 2, 1},
+    {32, 16, 4, 1}, {64, 32, 8, 1}, {64, 8, 2, 1},  {64, 16, 2, 2},
+    {64, 32, 2, 2}, {64, 16, 4, 2}, {64, 32, 4, 2}, {64, 8, 2, 2},
+    {64, 8, 4, 2},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -452,7 +410,7 @@ int tile_shape_count() { return kNumShapes; }
 TileShape tile_shape(int v) { return kShapes[v]; }
 
 // Blocks of a kernel that fit on the device at once.
-static int resident_blocks(const void* kernel, int threads) {
+int resident_blocks(const void* kernel, int threads) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
@@ -474,7 +432,7 @@ static hipError_t launch_mode(const StepArgs& a, hipStream_t st) {
       reinterpret_cast<const void*>(&k_step2d<TX, TZ, NTZ, MODE, PIPE>),
       TX * NTZ);
   const int items = a.g.ntiles * a.ngroups;
-  const int lim = a.resident_grid ? cap : items;
+  const int lim = (a.resident_grid & 1) ? cap : items;
   const int nblk = ((items < lim ? items : lim) + 7) / 8 * 8;
   hipLaunchKernelGGL((k_step2d<TX, TZ, NTZ, MODE, PIPE>), dim3(nblk),
                      dim3(TX, NTZ), 0, st, a);
@@ -507,6 +465,12 @@ hipError_t launch_step2d(int variant, int mode, const StepArgs& a,
     case 8: return launch_shape<32, 16, 4, true>(mode, a, st);
     case 9: return launch_shape<64, 32, 8, true>(mode, a, st);
     case 10: return launch_shape<64, 8, 2, true>(mode, a, st);
+    case 11: return launch_march2d(16, 2, mode, a, st);
+    case 12: return launch_march2d(32, 2, mode, a, st);
+    case 13: return launch_march2d(16, 4, mode, a, st);
+    case 14: return launch_march2d(32, 4, mode, a, st);
+    case 15: return launch_march2d(8, 2, mode, a, st);
+    case 16: return launch_march2d(8, 4, mode, a, st);
   }
   return hipErrorInvalidValue;
 }

@@ -441,7 +441,7 @@ static hipError_t launch3_mode(const StepArgs& a, hipStream_t st) {
   static const int cap = resident_blocks3(
       reinterpret_cast<const void*>(&k_step3d<TX, TY, SB, MODE>), TX * TY);
   const int items = a.g3.ntiles * a.ngroups;
-  const int lim = a.resident_grid ? cap : items;
+  const int lim = (a.resident_grid & 1) ? cap : items;
   const int nblk = ((items < lim ? items : lim) + 7) / 8 * 8;
   hipLaunchKernelGGL((k_step3d<TX, TY, SB, MODE>), dim3(nblk), dim3(TX, TY),
                      0, st, a);

@@ -70,8 +70,15 @@ def test_adjoint_matches_oracle(P, name, mode, ckpt):
     ctx.close()
 
 
+N_VARIANTS = 17
+
+
+def test_variant_list_is_covered(P):
+    assert len(P.tile_variants()) == N_VARIANTS
+
+
 @pytest.mark.parametrize("ckpt", [0, 5])
-@pytest.mark.parametrize("variant", range(11))
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
 def test_every_tile_shape_matches_oracle(P, variant, ckpt):
     w, idx = _case("ragged2d")
     print(f"tile variant {variant} ckpt={ckpt}", flush=True)
@@ -91,6 +98,50 @@ def test_every_tile_shape_matches_oracle(P, variant, ckpt):
         g = ctx.apply_adjoint(r)
         wg = prob.adjoint([x.astype(np.float64) for x in got], idx)
         assert rel(g, wg) <= OP_TOL
+    ctx.close()
+
+
+def _dense_receivers():
+    """Receivers at every column of two rows, each position twice, and one
+    more row at the bottom of the model: more entries on a strip row than a
+    wavefront has lanes."""
+    nz, nx, nb = 45, 150, 9
+    r = np.random.default_rng(33)
+    vel = 1800.0 + 600.0 * r.uniform(0, 1, (nz, nx))
+    m = r.uniform(-0.1, 0.1, (nz, nx))
+    shots = []
+    for i, (src, nt) in enumerate((((4, 0, 20), 220), ((30, 0, 140), 197))):
+        xs = np.arange(nx)
+        rows = [np.stack([np.full(nx, z), np.zeros(nx, int), xs], 1)
+                for z in (2, 2, 17, 17, nz - 1)]
+        rec = np.concatenate(rows, 0).astype(np.int32)
+        shots.append(synth.Shot(i, src, rec, nt, 24.0))
+    return synth.Workload("dense-receivers", -1, 2, nz, 1, nx, nb, 10.0,
+                          1e-3, 220, 24.0, vel[:, None, :].copy(),
+                          m[:, None, :].copy(), shots, Q=2, S=1, niter=4,
+                          lam_rel=0.01)
+
+
+@pytest.mark.parametrize("variant", [0, 6, 11, 12, 13, 14])
+def test_dense_receivers_match_oracle(P, variant):
+    w = _dense_receivers()
+    idx = [0, 1]
+    print(f"dense receivers variant {variant}", flush=True)
+    ctx = open_ctx(w, q_max=2)
+    ctx.set_tuning(variant, 2, 0, 2, 1)
+    for i in idx:
+        add_shot(ctx, w, i)
+    prob = oracle_problem(w)
+    m32 = f32(w.m_true)
+    got = split(w, idx, ctx.apply_born(m32))
+    want = prob.born(m32.astype(np.float64), idx)
+    for g_, w_ in zip(got, want):
+        assert rel(g_, w_) <= OP_TOL
+    r = [f32(synth.gaussian((w.shots[i].nt, w.shots[i].nrec), 40 + i))
+         for i in idx]
+    g = ctx.apply_adjoint(np.concatenate([x.ravel() for x in r]))
+    wg = prob.adjoint([x.astype(np.float64) for x in r], idx)
+    assert rel(g, wg) <= OP_TOL
     ctx.close()
 
 
@@ -293,10 +344,17 @@ def big():
     return w, idx
 
 
+def _bench_tuning():
+    import bench
+    return bench.DEFAULT_TUNING
+
+
 def test_full_size_born_shot_matches_oracle(P, big):
     w, idx = big
-    print("512x1024 born, 8-shot window, graph mode", flush=True)
+    print("512x1024 born, 8-shot window, graph mode, bench launch choice",
+          flush=True)
     ctx = open_ctx(w, q_max=8)
+    ctx.set_tuning(*_bench_tuning())
     for i in idx:
         add_shot(ctx, w, i)
     m32 = f32(w.m_true)
@@ -309,8 +367,10 @@ def test_full_size_born_shot_matches_oracle(P, big):
 
 def test_full_size_adjoint_shot_matches_oracle(P, big):
     w, idx = big
-    print("512x1024 adjoint, 8-shot window, graph mode", flush=True)
+    print("512x1024 adjoint, 8-shot window, graph mode, bench launch choice",
+          flush=True)
     ctx = open_ctx(w, q_max=8)
+    ctx.set_tuning(*_bench_tuning())
     for i in idx:
         add_shot(ctx, w, i)
     s = w.shots[7]
@@ -323,3 +383,31 @@ def test_full_size_adjoint_shot_matches_oracle(P, big):
     prob = oracle_problem(w, shots=[s])
     want = prob.adjoint_shot(0, r7.astype(np.float64))
     assert rel(got, want) <= OP_TOL
+
+
+def test_full_size_kernel_forms_agree(P, big):
+    """The staged-tile and z-marching kernels on the whole 8-shot window of
+    the 512 x 1024 model: the same arithmetic, so the operators agree to a
+    few float32 roundings (contractions may differ)."""
+    import torch
+    w, idx = big
+    ctx = open_ctx(w, q_max=8, device=True)
+    for i in idx:
+        s = w.shots[i]
+        ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+    m = torch.from_numpy(f32(w.m_true)).cuda()
+    r = torch.from_numpy(f32(synth.gaussian(ctx.window_data_size(), 88))
+                         ).cuda()
+    out = {}
+    for tune in ((0, 2, 1, 4, 0), (11, 1, 0, 2, 0), (12, 2, 1, 4, 0),
+                 (13, 1, 0, 2, 0), (14, 1, 1, 2, 1)):
+        print(f"512x1024 window, launch choice {tune}", flush=True)
+        ctx.set_tuning(*tune)
+        out[tune] = (ctx.apply_born(m).cpu().numpy(),
+                     ctx.apply_adjoint(r).cpu().numpy())
+    ctx.close()
+    ref = out[(0, 2, 1, 4, 0)]
+    for tune, (d, g) in out.items():
+        eb, ea = rel(d, ref[0]), rel(g, ref[1])
+        print(f"{tune}: born {eb:.2e} adjoint {ea:.2e}")
+        assert eb <= 2e-6 and ea <= 2e-6
