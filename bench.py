@@ -15,8 +15,10 @@ value = Born + adjoint grid-point updates per second over the timed steps
 background propagation not counted, time of everything in the step counted).
 
 Prints one JSON line. Also reports the roofline of the dominant kernel
-(event-timed in a separate pass) and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+(event-timed in a separate pass), the seconds per window solved to a fixed
+CG residual (batched graph launches and plain per-shot launches at the same
+residual), and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -35,16 +37,21 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # launch choice used unless --autotune is given (and by the counter runs):
 # tile variant, Born shots per block and grid shape, adjoint shots per block
 # and grid shape -- the fastest in a sweep of all choices on this workload
-# (z-marching wavefronts over 8-row chunks; adjoint work items in launch
-# order)
-DEFAULT_TUNING = (16, 1, 0, 4, 2)
+# (z-marching wavefronts taking two time steps per launch over 16-row
+# chunks, one shot per work item)
+DEFAULT_TUNING = (18, 1, 0, 1, 0)
+# with checkpointed backgrounds (no stored Born sources): the fastest
+# one-step choice
+DEFAULT_TUNING_CKPT = (16, 1, 0, 4, 2)
+# kernel behind each tile kind (the fourth number of a tile variant)
+KERNEL_NAME = {0: "k_step2d", 1: "k_step2d", 2: "k_march2d", 3: "k_march2t"}
 DEFAULT_TILE3 = 0
 
 # HBM bytes per launch of the 2-D step kernel under DEFAULT_TUNING, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --ops-only`, scaled
 # by the same counters on a 512 MiB copy (fetch x 2.000, write x 1.000).
-# Valid only for the kernel source they were taken on: reported as null
-# once stencil2d.hip or layout.h hash differently.
+# Valid only for the kernel sources they were taken on: reported as null
+# once the 2-D kernel sources hash differently.
 TRAFFIC_2D = {
     "sources_sha256_16": "3e1cb3211978a349",
     "born": 2 * 40019.4 * 1024 + 40880.0 * 1024,
@@ -55,7 +62,8 @@ TRAFFIC_2D = {
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("stencil2d.hip", "layout.h"):
+    for f in ("stencil2d.hip", "march2d.hip", "march2t.hip",
+              "march_common.h", "devutil.h", "layout.h"):
         with open(os.path.join(ROOT, "paper_1801_00819_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
@@ -82,6 +90,8 @@ def parse():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--fr-windows", type=int, default=3,
+                    help="windows solved to a fixed residual (0: skip)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch choice by timing (else the "
                          "built-in default)")
@@ -106,19 +116,76 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec):
-    """Bytes one batched time-step launch must move at minimum (float32):
-    per shot and padded point u read, v read, v write, u write (16 B) and
-    the Born-source cache on the model region (4 B); per block group the
+def algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec, steps=1):
+    """Bytes one batched launch must move at minimum (float32), the launch
+    advancing every shot by `steps` time steps (1, or 2 for the two-step
+    kernels): per shot and padded point u read, v read, v write, u write
+    (16 B, once per launch) and per step the Born-source frame on the model
+    region (4 B) and the receiver samples (4 B each); per block group the
     medium W' (4 B/point) and the model vector (Born: 4 B) or the float64
-    image accumulator read and written (adjoint: 16 B) on the model region;
-    per shot the receiver samples (4 B each)."""
-    per_shot = 16 * npad + 4 * nint + 4 * nrec
+    image accumulator read and written (adjoint: 16 B) on the model
+    region."""
+    per_shot = 16 * npad + steps * (4 * nint + 4 * nrec)
     if kind == "born":
         shared = 4 * npad + 4 * nint
     else:
         shared = 4 * npad + 16 * nint
     return Q * per_shot + ngroups * shared
+
+
+def fixed_residual(args, P, w, data, lam, vel, torch):
+    """Seconds per window solve at a fixed CG residual. The stop test is
+    ||A^T r - lambda m|| <= tau ||A^T d||, with tau the ratio the first
+    window (cold start) reaches after the configured iteration count. The
+    chain's first windows are solved to tau with the batched graph launches
+    and, the first of them, with plain per-shot launches."""
+    nrec = w.shots[0].nrec
+    windows = w.windows()
+
+    def chain(exec_mode, nwin, rtol, max_iter):
+        ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, w.nt, nrec, w.Q, w.h, w.dt,
+                          lam, vel, device=True)
+        ctx.set_tuning(*DEFAULT_TUNING)
+        ctx.set_exec(exec_mode)
+        held, stats = [], []
+        for k in range(nwin):
+            win = windows[k]
+            for i in list(held):
+                if i not in win:
+                    ctx.downdate(i)
+                    held.remove(i)
+            for i in win:
+                if i not in held:
+                    s = w.shots[i]
+                    ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+                    held.append(i)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = ctx.solve_window(max_iter, rtol)
+            torch.cuda.synchronize()
+            st["wall"] = time.perf_counter() - t
+            stats.append(st)
+            log(f"fixed residual ({'plain' if exec_mode == P.BRLS_EXEC_PLAIN else 'graph'}) "
+                f"window {k}: iters={st['iters']} s={st['wall']:.3f}")
+        ctx.close()
+        return stats
+
+    # tau from window 0 after the configured iterations (rtol tiny: the
+    # stop test never fires, but the solve reports ||A^T d||)
+    st0 = chain(P.BRLS_EXEC_GRAPH, 1, 1e-30, args.iters)[0]
+    tau = st0["s_norm"] / st0["ref_norm"]
+    g = chain(P.BRLS_EXEC_GRAPH, args.fr_windows, tau, 10 * args.iters)
+    p = chain(P.BRLS_EXEC_PLAIN, 1, tau, 10 * args.iters)
+
+    def summary(stats):
+        secs = [x["wall"] for x in stats]
+        return {"windows": len(stats),
+                "s_per_window_mean": round(float(np.mean(secs)), 4),
+                "s_per_window_max": round(float(np.max(secs)), 4),
+                "iters": [x["iters"] for x in stats]}
+    return {"tau": tau, "graph": summary(g), "plain": summary(p),
+            "plain_over_graph_first_window":
+                round(p[0]["wall"] / g[0]["wall"], 3)}
 
 
 def ops_only(P, w, vel, m_true):
@@ -280,7 +347,7 @@ def bench_autograd(args, P, synth, torch):
         for i in w.windows()[0]:
             s = w.shots[i]
             ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
-        ctx.set_tuning(*DEFAULT_TUNING)
+        ctx.set_tuning(*(DEFAULT_TUNING_CKPT if ck else DEFAULT_TUNING))
         d = ctx.apply_born(mt)
         m = (0.5 * mt).requires_grad_(True)
         misfit(m, d, ctx).backward()  # warm-up: graphs
@@ -499,22 +566,24 @@ def main():
     ks = ctx.kernel_stats()
     ctx.kernel_timing(False)
     var = tuning["variant"]
+    steps = 2 if P.tile_variants()[var][3] == 3 else 1  # steps per launch
     roof = {}
     for kind, name in (("born", "born_step"), ("adjoint", "adjoint_step")):
         n, ms = ks[name]
         avg_s = ms / n / 1e3
         pb = tuning["born_per_block" if kind == "born" else "adj_per_block"]
         ngroups = (Q + pb - 1) // pb
-        byt = algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec)
+        byt = algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec, steps)
         roof[kind] = dict(avg_us=avg_s * 1e6, bytes=byt,
                           gbs=byt / avg_s / 1e9)
     dom = max(roof, key=lambda k: roof[k]["avg_us"])
     r = roof[dom]
     out["roofline"] = {
         "bound": "hbm",
-        "kernel": f"{dom}_step (k_step2d, tile {P.tile_variants()[var]}, "
+        "kernel": f"{dom} launch ({KERNEL_NAME[P.tile_variants()[var][3]]}"
+                  f", tile {P.tile_variants()[var]}, "
                   f"{tuning['born_per_block' if dom == 'born' else 'adj_per_block']}"
-                  f" shots/block)",
+                  f" shots per work item, {steps} time step(s) per launch)",
         "achieved": round(r["gbs"], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -548,6 +617,12 @@ def main():
             for k, v in res.items()}
         log(f"operator pair: {out['operator_pair']}")
     ctx.close()
+
+    # ---- s per window at a fixed CG residual ----------------------------
+    if args.fr_windows > 0:
+        out["fixed_residual"] = fixed_residual(args, P, w, data, lam, vel,
+                                               torch)
+        log(f"fixed residual: {out['fixed_residual']}")
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample -------------
     if not args.no_cpu_baseline:

@@ -99,6 +99,7 @@ typedef struct {
   double s_norm;   /* same quantity at the end */
   double r_norm;   /* ||d - A m|| at the end */
   double seconds;  /* wall time of the call */
+  double ref_norm; /* ||A^T d|| when rtol > 0 (the stop test's scale), else 0 */
 } brls_stats;
 
 typedef struct {

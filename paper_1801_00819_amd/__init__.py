@@ -122,7 +122,8 @@ class Context:
         self._check(L.lib().brls_solve_window(self._h, int(max_iter),
                                               float(rtol), ctypes.byref(st)))
         return dict(iters=st.iters, s0_norm=st.s0_norm, s_norm=st.s_norm,
-                    r_norm=st.r_norm, seconds=st.seconds)
+                    r_norm=st.r_norm, seconds=st.seconds,
+                    ref_norm=st.ref_norm)
 
     solve_window = brls_solve_window
 

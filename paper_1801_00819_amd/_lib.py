@@ -57,7 +57,7 @@ class brls_shot(ctypes.Structure):
 class brls_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("s0_norm", ctypes.c_double),
                 ("s_norm", ctypes.c_double), ("r_norm", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("ref_norm", ctypes.c_double)]
 
 
 class brls_kstat(ctypes.Structure):

@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbrrlsm.so")
-SOURCES = ["stencil2d.hip", "march2d.hip", "stencil3d.hip", "blas.hip",
-           "engine.hip"]
+SOURCES = ["stencil2d.hip", "march2d.hip", "march2t.hip", "stencil3d.hip",
+           "blas.hip", "engine.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed fp32 instructions (v_pk_*_f32) in generated code

@@ -40,6 +40,7 @@ __device__ __forceinline__ ShotDev shot(const ShotDev* tab, int s) {
     d.f[k] = uni(d.f[k]);
     d.b[k] = uni(d.b[k]);
   }
+  d.f[3] = uni(d.f[3]);
   d.d2 = uni(d.d2);
   d.ck = uni(d.ck);
   d.rptr = uni(d.rptr);

@@ -175,6 +175,13 @@ hipMemcpyKind out_kind(const brls_ctx* c) {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// Propagated-field buffers per slot: u, u, v, and in 2-D with stored Born
+// sources a second v (the two-step kernels alternate between two sets).
+int fields_per_slot(const brls_ctx* c) {
+  return (c->ndim == 2 && !c->ckpt_k) ? 4 : 3;
+}
+
+
 int variant_count(const brls_ctx* c) {
   return c->ndim == 3 ? tile_shape3_count() : tile_shape_count();
 }
@@ -209,7 +216,11 @@ int receiver_bins(const brls_ctx* c) {
 // z), local index ly * TX + lx.
 int build_receiver_tiles(brls_ctx* c, Slot& sl) {
   const int nbins = receiver_bins(c);
-  std::vector<int> cnt(nbins + 1, 0), binof(sl.nrec), loc(sl.nrec);
+  struct Entry {
+    int bin, loc, rec;
+  };
+  std::vector<Entry> ms;  // (bin, local index, receiver) memberships
+  ms.reserve(sl.nrec);
   for (int j = 0; j < sl.nrec; ++j) {
     if (c->ndim == 3) {
       const TileShape3 ts = tile_shape3(c->variant);
@@ -217,26 +228,48 @@ int build_receiver_tiles(brls_ctx* c, Slot& sl) {
       const int pz = sl.rec[3 * j] + g.nb, py = sl.rec[3 * j + 1] + g.nb,
                 px = sl.rec[3 * j + 2] + g.nb;
       const int tyi = py / ts.ty, txi = (px - g.x_org) / ts.tx;
-      binof[j] = (tyi * g.ntx + txi) * g.pz + pz;
-      loc[j] = (py - tyi * ts.ty) * ts.tx + (px - g.x_org - txi * ts.tx);
-    } else {
-      const TileShape ts = tile_shape(c->variant);
-      const Geo2D& g = c->geo;
-      const int pz = sl.rec[3 * j] + g.nb, px = sl.rec[3 * j + 2] + g.nb;
-      const int tzi = pz / ts.tz, txi = (px - g.x_org) / ts.tx;
-      binof[j] = tzi * g.ntx + txi;
-      loc[j] = (pz - tzi * ts.tz) * ts.tx + (px - g.x_org - txi * ts.tx);
+      ms.push_back({(tyi * g.ntx + txi) * g.pz + pz,
+                    (py - tyi * ts.ty) * ts.tx + (px - g.x_org - txi * ts.tx),
+                    j});
+      continue;
     }
-    cnt[binof[j] + 1]++;
+    const TileShape ts = tile_shape(c->variant);
+    const Geo2D& g = c->geo;
+    const int pz = sl.rec[3 * j] + g.nb, px = sl.rec[3 * j + 2] + g.nb;
+    if (ts.pipe != 3) {
+      const int tzi = pz / ts.tz, txi = (px - g.x_org) / ts.tx;
+      ms.push_back({tzi * g.ntx + txi,
+                    (pz - tzi * ts.tz) * ts.tx + (px - g.x_org - txi * ts.tx),
+                    j});
+      continue;
+    }
+    // two-step tiles: every tile whose outputs widened by the 4-cell ring
+    // hold the receiver; local index (row - (z0 - 4)) * 64 +
+    // (column - (x0 - 4))
+    const int xr = px - g.x_org;
+    for (int tzi = std::max(0, pz / ts.tz - 1); tzi < g.ntz; ++tzi) {
+      const int z0 = tzi * ts.tz;
+      if (pz < z0 - kRadius) break;
+      if (pz >= z0 + ts.tz + kRadius) continue;
+      for (int txi = std::max(0, xr / ts.tx - 1); txi < g.ntx; ++txi) {
+        const int x0 = txi * ts.tx;  // relative to x_org
+        if (xr < x0 - kRadius) break;
+        if (xr >= x0 + ts.tx + kRadius) continue;
+        ms.push_back({tzi * g.ntx + txi,
+                      (pz - (z0 - kRadius)) * 64 + (xr - (x0 - kRadius)), j});
+      }
+    }
   }
+  std::vector<int> cnt(nbins + 1, 0);
+  for (const Entry& m : ms) cnt[m.bin + 1]++;
   for (int t = 0; t < nbins; ++t) cnt[t + 1] += cnt[t];
-  std::vector<int2> ent(std::max(sl.nrec, 1));
+  std::vector<int2> ent(std::max<size_t>(ms.size(), 1));
   std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
-  for (int j = 0; j < sl.nrec; ++j) {
+  for (const Entry& m : ms) {
     int2 e;
-    e.x = loc[j];
-    e.y = j;
-    ent[fillp[binof[j]]++] = e;
+    e.x = m.loc;
+    e.y = m.rec;
+    ent[fillp[m.bin]++] = e;
   }
   // each bin in local-index order (2-D: by row, then column), which the
   // z-marching kernels rely on
@@ -245,7 +278,7 @@ int build_receiver_tiles(brls_ctx* c, Slot& sl) {
                      [](const int2& p, const int2& q) { return p.x < q.x; });
   HIPCHECK(c, hipMemcpyAsync(sl.rptr, cnt.data(), sizeof(int) * cnt.size(),
                              hipMemcpyHostToDevice, c->st));
-  HIPCHECK(c, hipMemcpyAsync(sl.rent, ent.data(), sizeof(int2) * sl.nrec,
+  HIPCHECK(c, hipMemcpyAsync(sl.rent, ent.data(), sizeof(int2) * ms.size(),
                              hipMemcpyHostToDevice, c->st));
   HIPCHECK(c, hipStreamSynchronize(c->st));
   return BRLS_OK;
@@ -257,6 +290,7 @@ int64_t store_index(const brls_ctx* c, int z, int y, int x) {
 
 ShotDev shot_dev(const brls_ctx* c, const Slot& sl) {
   ShotDev d{};
+  d.f[3] = fields_per_slot(c) == 4 ? sl.fields + 3 * c->fs : nullptr;
   for (int k = 0; k < 3; ++k) {
     d.f[k] = sl.fields + k * c->fs;
     d.b[k] = (c->ckpt_k ? sl.bgf : sl.fields) + k * c->fs;
@@ -329,11 +363,19 @@ StepArgs base_args(const brls_ctx* c) {
   return a;
 }
 
-// One time step over `nshots` table entries starting at `tab`.
+// Whether the 2-D tile variant advances two time steps per launch.
+bool two_step(const brls_ctx* c) {
+  return c->ndim == 2 && tile_shape(c->variant).pipe == 3;
+}
+
+// One time step over `nshots` table entries starting at `tab` (two-step
+// variants: `nsub` steps, reading field set `par`).
 int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
          int per_block, const float* pm, float* dat, double* acc,
-         int d2_n0 = 0, int write_d2 = 0) {
+         int d2_n0 = 0, int write_d2 = 0, int nsub = 1, int par = 0) {
   StepArgs a = base_args(c);
+  a.nsub = nsub;
+  a.par = par;
   a.d2_n0 = d2_n0;
   a.write_d2 = write_d2;
   a.tab = tab;
@@ -357,7 +399,8 @@ int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
 }
 
 int64_t field_floats(const brls_ctx* c) {
-  return (int64_t)c->g.q_max * (c->ckpt_k ? 6 : 3) * c->fs;
+  return (int64_t)c->g.q_max * (fields_per_slot(c) + (c->ckpt_k ? 3 : 0)) *
+         c->fs;
 }
 
 int zero_fields(brls_ctx* c) {
@@ -383,7 +426,8 @@ int ensure_backgrounds(brls_ctx* c) {
   int rc;
   for (int i : todo) {
     Slot& sl = c->slots[i];
-    HIPCHECK(c, launch_fill_f32(c->ckpt_k ? sl.bgf : sl.fields, 3 * c->fs,
+    HIPCHECK(c, launch_fill_f32(c->ckpt_k ? sl.bgf : sl.fields,
+                                (c->ckpt_k ? 3 : fields_per_slot(c)) * c->fs,
                                 0.f, c->st));
   }
   const int ntm = nt_max_of(c, todo);
@@ -396,19 +440,21 @@ int ensure_backgrounds(brls_ctx* c) {
     HIPCHECK(c, launch_ckpt(tab, ns, n, n / c->ckpt_k, c->fs, 0, c->st));
     return BRLS_OK;
   };
+  // (two-step variants take the background one step per launch, the field
+  // sets alternating)
   if (c->exec == BRLS_EXEC_PLAIN) {
     for (int k = 0; k < nsh; ++k)
       for (int n = 0; n + 1 < c->slots[todo[k]].nt; ++n)
         if ((rc = save(c->bgtab_dev + k, 1, n)) ||
             (rc = step(c, kBackground, n, c->bgtab_dev + k, 1, 1, nullptr,
-                       nullptr, nullptr, 0, wr)))
+                       nullptr, nullptr, 0, wr, 1, n & 1)))
           return rc;
   } else {
     for (int n = 0; n + 1 < ntm; ++n)
       if ((rc = save(c->bgtab_dev, nsh, n)) ||
           (rc = step(c, kBackground, n, c->bgtab_dev, nsh,
                      std::min(c->per_block, nsh), nullptr, nullptr, nullptr,
-                     0, wr)))
+                     0, wr, 1, n & 1)))
         return rc;
   }
   HIPCHECK(c, hipStreamSynchronize(c->st));
@@ -426,31 +472,40 @@ int enqueue_born(brls_ctx* c, int batched) {
   const int mode = c->ckpt_k ? kBornFused : kBorn;
   int rc;
   if ((rc = zero_fields(c))) return rc;
+  // one step per launch, or two (levels n, n + 1; the field sets alternate)
+  const int dn = two_step(c) ? 2 : 1;
+  auto run = [&](const ShotDev* tab, int ns, int pb, int nt) -> int {
+    for (int n = 0, i = 0; n + 1 < nt; n += dn, ++i) {
+      const int r = step(c, mode, n, tab, ns, pb, c->born_in, c->q, nullptr,
+                         0, 0, std::min(dn, nt - 1 - n), i & 1);
+      if (r) return r;
+    }
+    return BRLS_OK;
+  };
   if (!batched) {
     for (int k = 0; k < nsh; ++k)
-      for (int n = 0; n + 1 < nt_max_of(c, {c->order[k]}); ++n)
-        if ((rc = step(c, mode, n, c->tab_dev + k, 1, 1, c->born_in, c->q,
-                       nullptr)))
-          return rc;
-  } else {
-    const int pb = std::min(c->per_block, nsh);
-    for (int n = 0; n + 1 < ntm; ++n)
-      if ((rc = step(c, mode, n, c->tab_dev, nsh, pb, c->born_in, c->q,
-                     nullptr)))
+      if ((rc = run(c->tab_dev + k, 1, 1, nt_max_of(c, {c->order[k]}))))
         return rc;
+  } else {
+    if ((rc = run(c->tab_dev, nsh, std::min(c->per_block, nsh), ntm)))
+      return rc;
   }
-  HIPCHECK(c, launch_born_last(c->tab_dev, nsh, c->g.nrec_max, c->q, c->st));
+  HIPCHECK(c, launch_born_last(c->tab_dev, nsh, c->g.nrec_max, c->q,
+                               two_step(c), c->st));
   return BRLS_OK;
 }
 
 // Adjoint steps k = k_hi .. k_lo (descending) of the shots in tab, the
 // Born-source frames of levels >= d2_n0 being available.
+// Two-step variants take levels k and k - 1 per launch, the field sets
+// alternating.
 int adjoint_steps(brls_ctx* c, const ShotDev* tab, int nsh, int pb, int k_hi,
                   int k_lo, int d2_n0) {
+  const int dk = two_step(c) ? 2 : 1;
   int rc;
-  for (int k = k_hi; k >= k_lo; --k)
+  for (int k = k_hi, i = 0; k >= k_lo; k -= dk, ++i)
     if ((rc = step(c, kAdjoint, k, tab, nsh, pb, nullptr, c->dscr, c->acc,
-                   d2_n0)))
+                   d2_n0, 0, std::min(dk, k - k_lo + 1), i & 1)))
       return rc;
   return BRLS_OK;
 }
@@ -655,9 +710,12 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   const StencilW sw = {(float)kW1, (float)kW2, (float)kW3, (float)kW4};
   const int x_org = (g.nb % 32 == 0) ? 0 : (g.nb % 32) - 32;
   const int px = g.nx + 2 * g.nb;
-  // x: first model column on a 128-byte boundary; room for every tile width
-  // (all divide 128) plus the 4-cell ring
-  const int pitch = round_up(32 - x_org + round_up(px - x_org, 128) + kGhost,
+  // x: first model column on a 128-byte boundary; room for the tile widths
+  // that divide 128 plus the 4-cell ring, and in 2-D 64 columns more (a
+  // two-step strip's wavefront and edge fills reach 64 columns past its
+  // last output)
+  const int pitch = round_up(32 - x_org + round_up(px - x_org, 128) + kGhost +
+                                 (g.ndim == 2 ? 64 : 0),
                              32);
   if (g.ndim == 3) {
     Geo3D& geo = c->geo3;
@@ -689,8 +747,9 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
     geo.x_org = x_org;
     geo.xoff = 32 - x_org;
     geo.pitch = pitch;
-    // z: room for tiles of up to 64 rows plus the ring
-    c->rows_alloc = round_up(geo.pz, 64) + 2 * kGhost;
+    // z: room for tiles of up to 64 rows plus the ring, and for chunk
+    // heights that do not divide 64 (rows past the grid are read as zeros)
+    c->rows_alloc = round_up(geo.pz, 64) + 24;
     c->fs = (int64_t)c->rows_alloc * geo.pitch;
     geo.eta_scale = eta_scale;
     geo.w = sw;
@@ -739,9 +798,10 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   c->slots.resize(g.q_max);
   for (int i = 0; i < g.q_max; ++i) {
     Slot& sl = c->slots[i];
-    sl.fields = c->fields_all + (int64_t)i * 3 * c->fs;
+    const int nf = fields_per_slot(c);
+    sl.fields = c->fields_all + (int64_t)i * nf * c->fs;
     if (c->ckpt_k)
-      sl.bgf = c->fields_all + ((int64_t)g.q_max + i) * 3 * c->fs;
+      sl.bgf = c->fields_all + ((int64_t)g.q_max * nf + (int64_t)i * 3) * c->fs;
     sl.dat_off = (int64_t)i * c->seg;
     if (c->ckpt_k) {
       ALLOC(sl.ck, (int64_t)c->nseg_max * 2 * c->fs);
@@ -751,7 +811,8 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
     }
     ALLOC(sl.wav, g.nt_max);
     ALLOC(sl.rptr, c->ntiles_max + 1);
-    ALLOC(sl.rent, g.nrec_max);
+    // a receiver lies in up to 4 tiles' widened regions (two-step tiles)
+    ALLOC(sl.rent, (int64_t)g.nrec_max * (g.ndim == 2 ? 4 : 1));
     ALLOC(sl.rsidx, g.nrec_max);
   }
 #undef ALLOC
@@ -972,6 +1033,7 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
     HIPCHECK(c, launch_dot(c->gbuf, c->gbuf, M, c->partial, c->scal, c->st));
     if ((rc = read_scalars(c, sc, 1))) return finish(rc);
     ref = std::sqrt(sc[0]);
+    st.ref_norm = ref;
   }
   HIPCHECK(c, hipMemcpyAsync(c->p, c->s, M * 4, hipMemcpyDeviceToDevice,
                              c->st));
@@ -1107,6 +1169,11 @@ static int set_tile_impl(brls_ctx* c, int v, int per_block,
                          int adj_per_block) {
   if (v < 0 || v >= variant_count(c))
     return fail(c, BRLS_EINVAL, "tile variant %d out of range", v);
+  if (c->ndim == 2 && c->ckpt_k && tile_shape(v).pipe == 3)
+    return fail(c, BRLS_EINVAL,
+                "tile variant %d takes two steps per launch and needs stored "
+                "Born sources (checkpoint interval 0)",
+                v);
   if (per_block < 1) per_block = 1;
   if (adj_per_block < 1) adj_per_block = 1;
   // 3-D kernels advance a fixed number of shots per block together
@@ -1181,6 +1248,7 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
     c->tune_nt = 400;
     float best_total = 1e30f;
     for (int v = 0; v < variant_count(c); ++v) {
+      if (c->ndim == 2 && c->ckpt_k && tile_shape(v).pipe == 3) continue;
       // the tile shape fixes the receiver lists; shots per block and grid
       // shape are chosen per operator
       float bt[2] = {1e30f, 1e30f};

@@ -33,16 +33,24 @@ hipError_t launch_adj_finalize3(const double* acc, int ngroups,
 // current device at once.
 int resident_blocks(const void* kernel, int threads);
 
-// z-marching 2-D step over chunks of cz rows (8, 16 or 32), the loads of
+// z-marching 2-D step over chunks of cz rows (8, 12, 16 or 32), the loads of
 // `ahead` rows (2 or 4) in flight ahead of the row computed.
 hipError_t launch_march2d(int cz, int ahead, int mode, const StepArgs& a,
+                          hipStream_t st);
+
+// Two time steps per launch (a.nsub of them), 2-D, chunks of cz = 16 rows,
+// the loads of `ahead` rows (2 or 4) in flight; background, Born and
+// adjoint modes.
+hipError_t launch_march2t(int cz, int ahead, int mode, const StepArgs& a,
                           hipStream_t st);
 
 // One time step for all shots of `a` (mode: StepMode).
 hipError_t launch_step2d(int variant, int mode, const StepArgs& a,
                          hipStream_t st);
+// d^{nt-1} of every shot (two_step: the last level sits in field set
+// ceil((nt-1)/2) mod 2, else (nt-1) mod 2).
 hipError_t launch_born_last(const ShotDev* tab, int nshots, int nrec_max,
-                            float* dat, hipStream_t st);
+                            float* dat, int two_step, hipStream_t st);
 hipError_t launch_adj_finalize(const double* acc, int ngroups,
                                const Geo2D& g, const float* wp, float* out,
                                hipStream_t st);

@@ -34,7 +34,10 @@ struct StencilW {
 // Per-shot state of a window slot, read by the kernels through a device
 // table in window order.
 struct ShotDev {
-  float* f[3];       // propagated field: u (even levels), u (odd levels), v
+  float* f[4];       // propagated field: u (even levels), u (odd levels), v;
+                     // two-step kernels: u and v in sets {f0, f2} and
+                     // {f1, f3}, alternating between launches (f3 is null
+                     // where the context keeps three fields)
   float* b[3];       // background field (same layout); may alias f
   float* d2;         // Born-source frames [..][model]; frame index n - d2_n0
   float* ck;         // background checkpoints [seg][u | v][field] or null
@@ -97,6 +100,9 @@ struct StepArgs {
                        // output level k (adjoint)
   int d2_n0;           // time level of stored frame 0
   int write_d2;        // background: store frames
+  int nsub;            // two-step kernels: time steps in this launch (1, 2)
+  int par;             // two-step kernels: field set read (0, 1); the other
+                       // is written
   int resident_grid;   // bit 0: launch only as many blocks as fit at once
                        // (each loops over work items), else one block per
                        // item; bit 1: deal work items to blocks in launch

@@ -342,12 +342,14 @@ __global__ void __launch_bounds__(TX* NTZ) k_step2d(StepArgs a) {
 }
 
 // Last sample of the Born data, d^{nt-1} = du^{nt-1} at the receivers.
-__global__ void k_born_last(const ShotDev* tab, int nshots, float* dat) {
+__global__ void k_born_last(const ShotDev* tab, int nshots, float* dat,
+                            int two_step) {
   const int s = blockIdx.y;
   if (s >= nshots) return;
   const ShotDev sd = tab[s];
   const int lvl = sd.nt - 1;
-  const float* u = (lvl & 1) ? sd.f[1] : sd.f[0];
+  const int set = two_step ? ((lvl + 1) >> 1) & 1 : lvl & 1;
+  const float* u = set ? sd.f[1] : sd.f[0];
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < sd.nrec;
        j += gridDim.x * blockDim.x)
     dat[sd.dat_off + (int64_t)lvl * sd.nrec + j] = u[sd.rsidx[j]];
@@ -396,13 +398,16 @@ __global__ void k_ckpt(const ShotDev* tab, int nshots, int n0, int seg,
 // kind 0 = staged tile, shots in turn; 1 = staged tile, the next shot's
 // loads issued before the current shot is computed; 2 = z-marching
 // wavefronts (march2d.hip: 64-column strips of TZ-row chunks; the third
-// number is then the rows of loads in flight ahead of the row computed).
+// number is then the rows of loads in flight ahead of the row computed);
+// 3 = z-marching with two time steps per launch (march2t.hip: 56 output
+// columns per strip).
 static const TileShape kShapes[] = {
     {64, 16, 4, 0}, {64, 32, 4, 0}, {64, 8, 2, 0},  {32, 32, 8, 0},
     {64, 32, 8, 0}, {32, 16, 4, 0}, {64, 16, 4, 1}, {32, 32, 8, 1},
     {32, 16, 4, 1}, {64, 32, 8, 1}, {64, 8, 2, 1},  {64, 16, 2, 2},
     {64, 32, 2, 2}, {64, 16, 4, 2}, {64, 32, 4, 2}, {64, 8, 2, 2},
-    {64, 8, 4, 2},
+    {64, 8, 4, 2},  {56, 16, 2, 3}, {56, 16, 4, 3}, {64, 12, 2, 2},
+    {64, 12, 4, 2},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -471,14 +476,19 @@ hipError_t launch_step2d(int variant, int mode, const StepArgs& a,
     case 14: return launch_march2d(32, 4, mode, a, st);
     case 15: return launch_march2d(8, 2, mode, a, st);
     case 16: return launch_march2d(8, 4, mode, a, st);
+    case 17: return launch_march2t(16, 2, mode, a, st);
+    case 18: return launch_march2t(16, 4, mode, a, st);
+    case 19: return launch_march2d(12, 2, mode, a, st);
+    case 20: return launch_march2d(12, 4, mode, a, st);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_born_last(const ShotDev* tab, int nshots, int nrec_max,
-                            float* dat, hipStream_t st) {
+                            float* dat, int two_step, hipStream_t st) {
   const dim3 grid((nrec_max + 255) / 256, nshots);
-  hipLaunchKernelGGL(k_born_last, grid, dim3(256), 0, st, tab, nshots, dat);
+  hipLaunchKernelGGL(k_born_last, grid, dim3(256), 0, st, tab, nshots, dat,
+                     two_step);
   return hipGetLastError();
 }
 
