@@ -53,9 +53,9 @@ DEFAULT_TILE3 = 0
 # Valid only for the kernel sources they were taken on: reported as null
 # once the 2-D kernel sources hash differently.
 TRAFFIC_2D = {
-    "sources_sha256_16": "3e1cb3211978a349",
-    "born": 2 * 40019.4 * 1024 + 40880.0 * 1024,
-    "adjoint": 2 * 38262.7 * 1024 + 49040.0 * 1024,
+    "sources_sha256_16": "688c72018a269383",
+    "born": 2 * 89550.4 * 1024 + 41406.1 * 1024,
+    "adjoint": 2 * 100045.9 * 1024 + 74365.3 * 1024,
 }
 
 
@@ -90,6 +90,12 @@ def parse():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--stream-shots", type=int, default=128,
+                    help="stream workload: shots taken from the 512")
+    ap.add_argument("--stream-iters", type=int, default=5,
+                    help="stream workload: CG iterations per window")
+    ap.add_argument("--stream-plain-windows", type=int, default=4,
+                    help="stream workload: windows run with plain launches")
     ap.add_argument("--fr-windows", type=int, default=3,
                     help="windows solved to a fixed residual (0: skip)")
     ap.add_argument("--autotune", action="store_true",
@@ -100,10 +106,11 @@ def parse():
     ap.add_argument("--only-steps", action="store_true",
                     help="time the steps only (for profiler runs)")
     ap.add_argument("--workload", default="2d",
-                    choices=["2d", "3d", "autograd"],
+                    choices=["2d", "3d", "autograd", "stream"],
                     help="2d: the window chain (default); 3d: the batched "
                          "3-D operator pair; autograd: differentiable Born "
-                         "with checkpointed backgrounds")
+                         "with checkpointed backgrounds; stream: ragged "
+                         "streaming windows, latency p50/p99")
     ap.add_argument("--ops-only", action="store_true",
                     help="after setup run one 512 MiB device copy (the "
                          "counter calibration kernel) and one batched Born "
@@ -403,6 +410,136 @@ def bench_autograd(args, P, synth, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_stream(args, P, synth, torch):
+    """Streaming uneven batching on the 512 x 1024 model: shots arrive in
+    sweeps of the 64 positions with apertures U{256..1024} receivers and nt
+    in {2000, 3000, 4000}, the reflectivity drifting 0.1 % per 64 shots.
+    For each window size Q in {4, 8, 16} (slide Q / 2) the warm-started
+    chain runs --stream-iters CG iterations per window over the first
+    --stream-shots shots; reported: per-window latency (downdate + update +
+    solve + image out) p50 / p99 with the batched graph launches, and with
+    plain per-shot launches on the first windows."""
+    nsh = args.stream_shots
+    base = synth.stream2d_512x1024(nshots=nsh, Q=8)
+    vel = base.vel.astype(np.float32)
+    nrec_max = max(s.nrec for s in base.shots)
+    nt_max = max(s.nt for s in base.shots)
+    # data d_i = A_i m_i + 1 % noise, m_i the drifting model; shots in
+    # batches of 8 that share the model of the batch's middle shot (the
+    # drift within a batch, 0.0125 %, is far below the noise)
+    t0 = time.perf_counter()
+    ctx = P.brls_open(2, base.nz, 1, base.nx, base.nb, nt_max, nrec_max, 8,
+                      base.h, base.dt, 0.0, vel, device=True)
+    ctx.set_tuning(*DEFAULT_TUNING)
+    data = []
+    for b in range(0, nsh, 8):
+        ids = list(range(b, min(b + 8, nsh)))
+        for i in ids:
+            s = base.shots[i]
+            ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+        mb = torch.from_numpy(synth.model_at(base, ids[len(ids) // 2])
+                              .astype(np.float32)).cuda()
+        d = ctx.apply_born(mb)
+        off = 0
+        for i in ctx.window():
+            s = base.shots[i]
+            n = s.nt * s.nrec
+            data.append((i, d[off:off + n].view(s.nt, s.nrec).clone()))
+            off += n
+        for i in ids:
+            ctx.downdate(i)
+    ctx.close()
+    data = [x for _, x in sorted(data, key=lambda t: t[0])]
+    rms = float(np.sqrt(sum(float((x.double() ** 2).sum()) for x in data)
+                        / sum(x.numel() for x in data)))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4001)
+    for x in data:
+        x += 0.01 * rms * torch.randn(x.shape, generator=gen, device="cuda")
+    log(f"stream: data for {nsh} shots in {time.perf_counter() - t0:.1f}s")
+
+    def run(Q, exec_mode, nwin):
+        w = synth.stream2d_512x1024(nshots=nsh, Q=Q)
+        wins = w.windows()[:nwin]
+        c = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt_max, nrec_max, Q, w.h,
+                        w.dt, 0.0, vel, device=True)
+        c.set_tuning(*DEFAULT_TUNING)
+        # lambda: relative 1e-3 of ||A^T A|| on the first window (power
+        # iteration, 4 steps)
+        for i in wins[0]:
+            s = w.shots[i]
+            c.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+        x = torch.from_numpy(synth.gaussian(w.model_shape, 2002)
+                             .astype(np.float32)).cuda()
+        x /= torch.linalg.vector_norm(x)
+        nrm = 0.0
+        for _ in range(4):
+            y = c.apply_adjoint(c.apply_born(x))
+            nrm = float(torch.linalg.vector_norm(y.double()))
+            x = y / nrm
+        c.close()
+        c = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt_max, nrec_max, Q, w.h,
+                        w.dt, w.lam_rel * nrm, vel, device=True)
+        c.set_tuning(*DEFAULT_TUNING)
+        c.set_exec(exec_mode)
+        image = torch.empty(w.model_shape, dtype=torch.float32, device="cuda")
+        held, lat, its = [], [], []
+        for win in wins:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for i in list(held):
+                if i not in win:
+                    c.downdate(i)
+                    held.remove(i)
+            for i in win:
+                if i not in held:
+                    s = w.shots[i]
+                    c.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+                    held.append(i)
+            st = c.solve_window(args.stream_iters)
+            c.image(image)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t)
+            its.append(st["iters"])
+        c.close()
+        return lat, len(w.windows())
+
+    per_q = {}
+    for Q in (4, 8, 16):
+        lat, total = run(Q, P.BRLS_EXEC_GRAPH, 10 ** 9)
+        plain, _ = run(Q, P.BRLS_EXEC_PLAIN, args.stream_plain_windows)
+        # the first window of each run includes graph capture and the
+        # backgrounds of all Q shots; latencies are over the later windows
+        steady = lat[1:] if len(lat) > 1 else lat
+        per_q[Q] = {
+            "windows": len(lat),
+            "p50_s": round(float(np.percentile(steady, 50)), 4),
+            "p99_s": round(float(np.percentile(steady, 99)), 4),
+            "mean_s": round(float(np.mean(steady)), 4),
+            "first_window_s": round(lat[0], 4),
+            "plain_windows": len(plain),
+            "plain_p50_s": round(float(np.percentile(plain[1:] or plain,
+                                                      50)), 4),
+        }
+        log(f"stream Q={Q}: {per_q[Q]}")
+    out = {
+        "metric": "window solve latency p50 (Q=8)",
+        "value": per_q[8]["p50_s"],
+        "unit": "s",
+        "n_gpus": 1, "steps": per_q[8]["windows"], "warmup": 0,
+        "ms_per_step": round(per_q[8]["mean_s"] * 1e3, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"stream2d-512x1024: first {nsh} of 512 "
+                               "shots, apertures 256-1024, nt 2000/3000/"
+                               f"4000, slide Q/2, {args.stream_iters} CG "
+                               "iterations per window, drift 0.1 % per 64 "
+                               "shots"},
+        "per_window_size": {str(k): v for k, v in per_q.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -420,6 +557,8 @@ def main():
         return bench_3d(args, P, synth, torch)
     if args.workload == "autograd":
         return bench_autograd(args, P, synth, torch)
+    if args.workload == "stream":
+        return bench_stream(args, P, synth, torch)
     w = synth.faulted2d_512x1024()
     Q, S = w.Q, w.S
     nshots = len(w.shots)
@@ -438,6 +577,7 @@ def main():
     t_setup = time.perf_counter()
     ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt, nrec, Q, w.h, w.dt, 0.0,
                       vel, device=True)
+    ctx.set_tuning(*DEFAULT_TUNING)
     data = torch.empty((nshots, nt, nrec), dtype=torch.float32, device="cuda")
     for b in range(0, nshots, Q):
         ids = list(range(b, min(b + Q, nshots)))

@@ -12,7 +12,10 @@ from .configs import (  # noqa: F401
     layers2d_64x64,
     faulted2d_512x1024,
     layered3d_256x320x320,
+    model_at,
     noise_like,
+    stream2d_512x1024,
+    streaming,
     tiny2d,
     tiny3d,
     rng,

@@ -26,6 +26,7 @@ import numpy as np
 SEED_LAYERS2D_64 = 0
 SEED_FAULTED2D_512 = 1
 SEED_LAYERED3D_256 = 3
+SEED_STREAM2D_512 = 4
 
 
 def rng(seed_group: int, stream: int) -> np.random.Generator:
@@ -265,6 +266,75 @@ def tiny3d(nz: int = 8, ny: int = 8, nx: int = 8, nb: int = 4, nt: int = 80,
     return Workload("tiny3d", -1, 3, nz, ny, nx, nb, 10.0, 1e-3, nt, 30.0,
                     np.ascontiguousarray(vel), m, shots, Q=nshots, S=1,
                     niter=10, lam_rel=0.01)
+
+
+def _smooth(a: np.ndarray, half: int) -> np.ndarray:
+    """Moving average over 2 * half + 1 cells along each axis (edges
+    replicated), applied twice."""
+    out = a
+    for _ in range(2):
+        for ax in range(out.ndim):
+            if out.shape[ax] == 1:
+                continue
+            pad = [(0, 0)] * out.ndim
+            pad[ax] = (half, half)
+            c = np.cumsum(np.pad(out, pad, mode="edge"), axis=ax)
+            c = np.insert(c, 0, 0.0, axis=ax)
+            n = out.shape[ax]
+            hi = np.take(c, np.arange(2 * half + 1, 2 * half + 1 + n), axis=ax)
+            lo = np.take(c, np.arange(0, n), axis=ax)
+            out = (hi - lo) / (2 * half + 1)
+    return out
+
+
+def streaming(base: Workload, nshots: int, Q: int, apertures, nts,
+              seed_group: int, positions=None, niter: int = 5,
+              drift_per_64: float = 1e-3) -> Workload:
+    """A stream of shots over `base`'s model: shot i sits at position
+    i mod len(positions) (default: base's shot positions, in sweeps), with
+    a contiguous receiver aperture of n_r ~ U{apertures} cells centred on
+    the source (clipped to the model) on base's receiver row, and nt drawn
+    from `nts`. The reflectivity drifts: shot i sees
+        m_i = m_0 + (i / 64) * drift,  ||drift|| = drift_per_64 ||m_0||,
+    with drift a seeded Gaussian field smoothed over 4 cells (base.extra
+    keeps m_0 in m_true; `drift` goes to extra). Windows of Q shots slide
+    by Q / 2."""
+    r = rng(seed_group, 3)
+    nx = base.nx
+    zr = int(base.shots[0].rec[0, 0])
+    pos = positions if positions is not None else [s.src for s in base.shots]
+    lo_a, hi_a = apertures
+    shots = []
+    for i in range(nshots):
+        src = pos[i % len(pos)]
+        nr = int(min(r.integers(lo_a, hi_a + 1), nx))
+        x0 = int(np.clip(src[2] - nr // 2, 0, nx - nr))
+        rec = _row_receivers(zr, range(x0, x0 + nr))
+        nt = int(r.choice(nts))
+        shots.append(Shot(i, tuple(src), rec, nt, base.f0))
+    d = _smooth(r.standard_normal(base.model_shape), 4)
+    d *= drift_per_64 * np.linalg.norm(base.m_true) / np.linalg.norm(d)
+    extra = dict(base.extra)
+    extra["drift"] = d
+    return Workload(base.name + "-stream", seed_group, base.ndim, base.nz,
+                    base.ny, base.nx, base.nb, base.h, base.dt,
+                    max(s.nt for s in shots), base.f0, base.vel, base.m_true,
+                    shots, Q=Q, S=max(1, Q // 2), niter=niter,
+                    lam_rel=base.lam_rel, extra=extra)
+
+
+def stream2d_512x1024(nshots: int = 512, Q: int = 8) -> Workload:
+    """Streaming form of the faulted 512 x 1024 workload: `nshots` shots in
+    sweeps of its 64 positions, apertures U{256..1024} receivers, nt in
+    {2000, 3000, 4000}, reflectivity drifting 0.1 % per 64 shots."""
+    return streaming(faulted2d_512x1024(), nshots, Q, (256, 1024),
+                     (2000, 3000, 4000), SEED_STREAM2D_512)
+
+
+def model_at(w: Workload, i: int) -> np.ndarray:
+    """The reflectivity shot i sees (streaming workloads drift)."""
+    d = w.extra.get("drift")
+    return w.m_true if d is None else w.m_true + (i / 64.0) * d
 
 
 def noise_like(shape, seed_group: int) -> np.ndarray:

@@ -419,3 +419,39 @@ def test_full_size_kernel_forms_agree(P, big):
         eb, ea = rel(d, ref[0]), rel(g, ref[1])
         print(f"{tune}: born {eb:.2e} adjoint {ea:.2e}")
         assert eb <= 2e-6 and ea <= 2e-6
+
+
+def _small_stream():
+    """A stream of 10 shots over the 64 x 64 model: apertures of 16..48
+    receivers, nt in {300, 400, 500}, drifting reflectivity, windows of 4
+    sliding by 2, 3 CG iterations per window."""
+    return synth.streaming(synth.layers2d_64x64(), 10, 4, (16, 48),
+                           (300, 400, 500), 40, niter=3)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_streaming_chain_matches_oracle(P, mode):
+    """Ragged stream (per-shot nt and aperture, per-shot drifting model),
+    rank-2 update and downdate per window, warm-started, with the bench's
+    launch choice: final image vs the oracle chain."""
+    import oracle
+    w = _small_stream()
+    prob = oracle_problem(w)
+    clean = [prob.born_shot(i, f32(synth.model_at(w, i)).astype(np.float64))
+             for i in range(len(w.shots))]
+    sig = w.noise_rel * np.sqrt(np.mean(np.concatenate(
+        [c.ravel() for c in clean]) ** 2))
+    data = [f32(c + sig * synth.gaussian(c.shape, 4100 + i))
+            for i, c in enumerate(clean)]
+    wins = w.windows()
+    lam = w.lam_rel * oracle.power_norm(prob, wins[0], 10, seed=3)
+    ref = oracle.chain(prob, [d.astype(np.float64) for d in data], wins, lam,
+                       w.niter)
+    print(f"stream: {len(wins)} windows, nt {[s.nt for s in w.shots]}, "
+          f"nrec {[s.nrec for s in w.shots]}, exec mode {mode}", flush=True)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    ctx.set_tuning(*_bench_tuning())
+    ctx.set_exec(mode)
+    img = _gpu_chain(ctx, w, data, w.niter)
+    ctx.close()
+    assert rel(img, ref.m) <= IMG_TOL
