@@ -16,7 +16,12 @@ What it computes (Kazemi & Sacchi, arXiv 1801.00819):
   * ``chain``: the block-row recursion of eqs. 10-11: windows of Q shots
     sliding by S (rank-S update and downdate), each window's CG warm-started
     from the previous window's image (the reading used for eq. 11 regularises
-    the whole image, so each window solves eq. 10 exactly as posed).
+    the whole image, so each window solves eq. 10 exactly as posed);
+  * ``illumination`` / ``illumination_minv``: the diagonal preconditioner the
+    paper asks for in each window's CG (it names none; this build's reading:
+    the source-side illumination sum over the window's shots and time levels
+    of (D2 u0^n)^2, inverted with a stabiliser of 1 % of its mean), used by
+    ``cgls(..., minv=...)``.
 """
 from __future__ import annotations
 
@@ -252,28 +257,37 @@ class CGLSResult:
 
 def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
          lam: float, niter: int, m0: Optional[np.ndarray] = None,
-         rtol: float = 0.0, keep_iterates: bool = False) -> CGLSResult:
+         rtol: float = 0.0, keep_iterates: bool = False,
+         minv: Optional[np.ndarray] = None) -> CGLSResult:
     """CG on min ||A m - d||^2 + lam ||m||^2 (eq. 3 / eq. 10), least-squares
     form: one A and one A^T per iteration, all in FP64.
 
+    With ``minv`` (the inverse of a positive diagonal preconditioner M, model
+    shaped) this is preconditioned CG on the normal equations
+    (A^T A + lam I) m = A^T d: the search direction follows M^{-1} s, with
+    gamma = <s, M^{-1} s>.
+
     Stops after ``niter`` iterations, or earlier once
-    ||A^T r - lam m|| <= rtol * ||A^T d||."""
+    ||A^T r - lam m|| <= rtol * ||A^T d|| (s unpreconditioned in both)."""
     m = np.zeros(prob.grid.model_shape) if m0 is None else np.array(
         m0, dtype=np.float64).reshape(prob.grid.model_shape)
     d = [np.asarray(x, dtype=np.float64) for x in d]
+    w = None if minv is None else np.asarray(
+        minv, dtype=np.float64).reshape(prob.grid.model_shape)
     Am = prob.born(m, idx)
     r = [di - ai for di, ai in zip(d, Am)]
     s = prob.adjoint(r, idx) - lam * m
-    p = s.copy()
-    gamma = float(np.vdot(s, s))
-    s0 = np.sqrt(gamma)
+    z = s if w is None else w * s
+    p = z.copy()
+    gamma = float(np.vdot(s, z))
+    snorm = float(np.linalg.norm(s))
     ref = None
     if rtol > 0:
         ref = np.linalg.norm(prob.adjoint(d, idx))
-    res = CGLSResult(m, 0, s0, [s0], [np.sqrt(_dot(r, r))], [], [],
+    res = CGLSResult(m, 0, snorm, [snorm], [np.sqrt(_dot(r, r))], [], [],
                      [m.copy()] if keep_iterates else None)
     for k in range(niter):
-        if ref is not None and np.sqrt(gamma) <= rtol * ref:
+        if ref is not None and snorm <= rtol * ref:
             break
         if gamma == 0.0:
             break
@@ -285,19 +299,42 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
         m = m + alpha * p
         r = [ri - alpha * qi for ri, qi in zip(r, q)]
         s = prob.adjoint(r, idx) - lam * m
-        gamma_new = float(np.vdot(s, s))
+        z = s if w is None else w * s
+        gamma_new = float(np.vdot(s, z))
         beta = gamma_new / gamma
-        p = s + beta * p
+        p = z + beta * p
         gamma = gamma_new
+        snorm = float(np.linalg.norm(s))
         res.iters += 1
         res.alphas.append(alpha)
         res.betas.append(beta)
-        res.s_norms.append(np.sqrt(gamma))
+        res.s_norms.append(snorm)
         res.r_norms.append(np.sqrt(_dot(r, r)))
         if keep_iterates:
             res.iterates.append(m.copy())
     res.m = m
     return res
+
+
+def illumination(prob: Problem, idx: Sequence[int]) -> np.ndarray:
+    """Source-side illumination of a window: at each model point, the sum
+    over the window's shots and over the time levels n = 0 .. nt-2 of the
+    squared Born source (D2 u0^n)^2 (the stored frames of eq. F2)."""
+    acc = np.zeros(int(np.prod(prob.grid.model_shape)))
+    for i in idx:
+        d2, _ = prob.background_shot(i, want_d2u0=True, want_rec=False)
+        acc += np.sum(d2 * d2, axis=0)
+    return acc.reshape(prob.grid.model_shape)
+
+
+# stabiliser of the illumination preconditioner, relative to the mean
+ILLUM_EPS = 0.01
+
+
+def illumination_minv(illum: np.ndarray) -> np.ndarray:
+    """Inverse diagonal preconditioner 1 / (I + ILLUM_EPS * mean(I))."""
+    illum = np.asarray(illum, dtype=np.float64)
+    return 1.0 / (illum + ILLUM_EPS * float(np.mean(illum)))
 
 
 @dataclass

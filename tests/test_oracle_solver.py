@@ -171,3 +171,97 @@ def test_paper_window_schedule():
     for a, b in zip(wins, wins[1:-1]):
         assert len(set(a) - set(b)) == K and len(set(b) - set(a)) == K
     assert wins[-1][-1] == N - 1
+
+
+# --- preconditioned window CG (diagonal illumination) -------------------
+
+def _textbook_pcg(H, b, x0, minv, niter):
+    """Preconditioned CG on H x = b with the diagonal preconditioner
+    M = diag(1 / minv)."""
+    x = x0.copy()
+    r = b - H @ x
+    z = minv * r
+    p = z.copy()
+    rz = r @ z
+    xs = [x.copy()]
+    for _ in range(niter):
+        Hp = H @ p
+        a = rz / (p @ Hp)
+        x = x + a * p
+        r = r - a * Hp
+        z = minv * r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        xs.append(x.copy())
+    return xs
+
+
+def test_pcg_with_identity_is_plain_cgls(orc, dense_problem):
+    dp = dense_problem
+    idx = [0, 1]
+    data = [dp["data"][i] for i in idx]
+    a = orc.cgls(dp["prob"], idx, data, dp["lam"], 6, keep_iterates=True)
+    b = orc.cgls(dp["prob"], idx, data, dp["lam"], 6, keep_iterates=True,
+                 minv=np.ones(dp["prob"].grid.model_shape))
+    for xa, xb in zip(a.iterates, b.iterates):
+        assert np.linalg.norm(xa - xb) <= 1e-13 * max(np.linalg.norm(xa),
+                                                      1e-300)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_pcg_iterates_equal_textbook_pcg(orc, dense_problem, warm):
+    """The preconditioned least-squares recurrences against preconditioned
+    CG on the dense normal matrix (eq. 4), with the illumination
+    preconditioner of the window."""
+    dp = dense_problem
+    idx = [0, 2]
+    A, d, H, b = _normal(dp, idx)
+    minv = orc.illumination_minv(orc.illumination(dp["prob"], idx)).ravel()
+    assert np.all(minv > 0) and np.ptp(minv) > 0
+    x0 = synth.gaussian(dp["M"], 6) * 0.05 if warm else np.zeros(dp["M"])
+    ref = _textbook_pcg(H, b, x0, minv, 8)
+    res = orc.cgls(dp["prob"], idx, [dp["data"][i] for i in idx], dp["lam"],
+                   8, m0=x0.reshape(dp["prob"].grid.model_shape),
+                   keep_iterates=True,
+                   minv=minv.reshape(dp["prob"].grid.model_shape))
+    assert res.iters == 8
+    for k, (xr, xo) in enumerate(zip(ref, res.iterates)):
+        rel = np.linalg.norm(xo.ravel() - xr) / max(np.linalg.norm(xr), 1e-300)
+        assert rel < 1e-10, (k, rel)
+
+
+def test_pcg_converges_to_closed_form(orc, dense_problem):
+    dp = dense_problem
+    idx = [0, 1, 2]
+    A, d, H, b = _normal(dp, idx)
+    minv = orc.illumination_minv(orc.illumination(dp["prob"], idx))
+    res = orc.cgls(dp["prob"], idx, [dp["data"][i] for i in idx], dp["lam"],
+                   150, minv=minv)
+    exact = np.linalg.solve(H, b)
+    assert np.linalg.norm(res.m.ravel() - exact) <= 1e-9 * np.linalg.norm(
+        exact)
+
+
+def test_illumination_from_recorded_background(orc):
+    """The illumination from the background's stored Born-source frames
+    equals the same sum formed from the background wavefield recorded at
+    every model point (second differences in time taken here)."""
+    w = synth.tiny2d(nz=7, nx=8, nb=4, nt=90, nrec=4, nshots=2, seed=9)
+    nz, nx = w.nz, w.nx
+    zz, xx = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    every = np.stack([zz.ravel(), np.zeros(zz.size, int), xx.ravel()],
+                     1).astype(np.int32)
+    shots = [synth.Shot(s.id, s.src, every, s.nt, s.f0) for s in w.shots]
+    prob = orc.Problem(orc.Grid(2, nz, 1, nx, w.nb, w.h, w.dt),
+                       w.vel.astype(np.float64), shots)
+    want = np.zeros(nz * nx)
+    for i in range(len(shots)):
+        _, u = prob.background_shot(i, want_d2u0=False, want_rec=True)
+        # u^{-1} = 0: pad one zero level in front
+        u = np.concatenate([np.zeros((1, u.shape[1])), u], 0)
+        d2 = u[2:] - 2 * u[1:-1] + u[:-2]          # levels n = 0 .. nt-2
+        want += np.sum(d2 * d2, axis=0)
+    got = orc.illumination(prob, [0, 1]).ravel()
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    assert np.all(got >= 0)
