@@ -145,15 +145,17 @@ def fixed_residual(args, P, w, data, lam, vel, torch):
     ||A^T r - lambda m|| <= tau ||A^T d||, with tau the ratio the first
     window (cold start) reaches after the configured iteration count. The
     chain's first windows are solved to tau with the batched graph launches
-    and, the first of them, with plain per-shot launches."""
+    (plain CG, and CG preconditioned by the window's illumination) and, the
+    first of them, with plain per-shot launches."""
     nrec = w.shots[0].nrec
     windows = w.windows()
 
-    def chain(exec_mode, nwin, rtol, max_iter):
+    def chain(exec_mode, nwin, rtol, max_iter, precond=0):
         ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, w.nt, nrec, w.Q, w.h, w.dt,
                           lam, vel, device=True)
         ctx.set_tuning(*DEFAULT_TUNING)
         ctx.set_exec(exec_mode)
+        ctx.set_precond(precond)
         held, stats = [], []
         for k in range(nwin):
             win = windows[k]
@@ -172,7 +174,8 @@ def fixed_residual(args, P, w, data, lam, vel, torch):
             torch.cuda.synchronize()
             st["wall"] = time.perf_counter() - t
             stats.append(st)
-            log(f"fixed residual ({'plain' if exec_mode == P.BRLS_EXEC_PLAIN else 'graph'}) "
+            log(f"fixed residual ({'plain' if exec_mode == P.BRLS_EXEC_PLAIN else 'graph'}"
+                f"{', preconditioned' if precond else ''}) "
                 f"window {k}: iters={st['iters']} s={st['wall']:.3f}")
         ctx.close()
         return stats
@@ -183,6 +186,8 @@ def fixed_residual(args, P, w, data, lam, vel, torch):
     tau = st0["s_norm"] / st0["ref_norm"]
     g = chain(P.BRLS_EXEC_GRAPH, args.fr_windows, tau, 10 * args.iters)
     p = chain(P.BRLS_EXEC_PLAIN, 1, tau, 10 * args.iters)
+    pc = chain(P.BRLS_EXEC_GRAPH, args.fr_windows, tau, 10 * args.iters,
+               precond=1)
 
     def summary(stats):
         secs = [x["wall"] for x in stats]
@@ -192,7 +197,8 @@ def fixed_residual(args, P, w, data, lam, vel, torch):
                 "iters": [x["iters"] for x in stats]}
     return {"tau": tau, "graph": summary(g), "plain": summary(p),
             "plain_over_graph_first_window":
-                round(p[0]["wall"] / g[0]["wall"], 3)}
+                round(p[0]["wall"] / g[0]["wall"], 3),
+            "graph_illumination_preconditioned": summary(pc)}
 
 
 def ops_only(P, w, vel, m_true):

@@ -164,6 +164,22 @@ int brls_image(brls_ctx* ctx, float* out);
 /* Set the current image (e.g. resume, or an explicit start). */
 int brls_set_image(brls_ctx* ctx, const float* m);
 
+/* Preconditioner of brls_solve_window. The paper asks for one in each
+ * window's CG (to cluster the normal operator's eigenvalues near 1) and
+ * names none; mode 1 is this library's diagonal one: M = I + 0.01 mean(I),
+ * I the window's source-side illumination (brls_illumination), and the CG
+ * runs preconditioned (directions follow M^-1 s, gamma = <s, M^-1 s>; the
+ * stop test keeps ||s||). Mode 0 (default): none. Mode 1 needs stored Born
+ * sources (ckpt_interval 0); otherwise BRLS_EINVAL. */
+int brls_set_precond(brls_ctx* ctx, int32_t mode);
+int brls_get_precond(const brls_ctx* ctx, int32_t* mode);
+
+/* The window's illumination [nz][ny][nx]: at each model point the sum over
+ * the window's shots and time levels n = 0 .. nt-2 of (D2 u0^n)^2, the
+ * squared Born source of eq. 1's linearisation (F2). Needs stored Born
+ * sources (BRLS_EINVAL otherwise). out: host or device per flags. */
+int brls_illumination(brls_ctx* ctx, float* out);
+
 /* Eq. 1 without noise on the current window: d_out = A_w m (window data
  * layout, brls_window_data_size floats). */
 int brls_apply_born(brls_ctx* ctx, const float* m, float* d_out);

@@ -150,6 +150,27 @@ class Context:
 
     set_image = brls_set_image
 
+    def brls_set_precond(self, mode: int):
+        """0: plain CG; 1: diagonal illumination preconditioner."""
+        self._check(L.lib().brls_set_precond(self._h, int(mode)))
+
+    set_precond = brls_set_precond
+
+    def brls_get_precond(self) -> int:
+        v = ctypes.c_int32()
+        self._check(L.lib().brls_get_precond(self._h, ctypes.byref(v)))
+        return v.value
+
+    get_precond = brls_get_precond
+
+    def brls_illumination(self, out=None):
+        out = self._model_out(out)
+        self._check(L.lib().brls_illumination(self._h,
+                                              _ptr(out, self.device)))
+        return out
+
+    illumination = brls_illumination
+
     def brls_apply_born(self, m, out=None):
         if not self.device:
             m = np.ascontiguousarray(m, dtype=np.float32)

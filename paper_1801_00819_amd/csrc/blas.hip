@@ -92,6 +92,44 @@ __global__ void k_nonfinite(const float* x, int64_t n, int* flag) {
   if (bad) atomicOr(flag, 1);
 }
 
+// out[i] = sum over frames f of x[f][i]^2 (float64 sum), x [nframes][n].
+__global__ void k_sumsq_frames(const float* x, int64_t nframes, int64_t n,
+                               float* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    const float* p = x + i;
+    for (int64_t f = 0; f < nframes; ++f, p += n) {
+      const double v = (double)__builtin_nontemporal_load(p);
+      acc += v * v;
+    }
+    out[i] = (float)acc;
+  }
+}
+
+__global__ void k_mul(float* z, const float* a, const float* b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = a[i] * b[i];
+}
+
+__global__ void k_recip_shift(float* y, const float* x, double shift,
+                              int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)(1.0 / ((double)x[i] + shift));
+}
+
+__global__ void __launch_bounds__(256)
+    k_sum_partial(const float* a, int64_t n, double* part) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)a[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 static int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 8192) b = 8192;
@@ -148,6 +186,38 @@ hipError_t launch_grad_norm(float* s, const float* g, const float* m,
                             double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_grad_norm, dim3(kDotBlocks), dim3(256), 0, st, s, g, m,
                      lambda, n, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial,
+                     kDotBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq_frames(const float* x, int64_t nframes, int64_t n,
+                               float* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sumsq_frames, dim3(grid_for(n)), dim3(256), 0, st, x,
+                     nframes, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul(float* z, const float* a, const float* b, int64_t n,
+                      hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(256), 0, st, z, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_recip_shift(float* y, const float* x, double shift,
+                              int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_recip_shift, dim3(grid_for(n)), dim3(256), 0, st, y, x,
+                     shift, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const float* x, int64_t n, double* partial, double* out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partial, dim3(kDotBlocks), dim3(256), 0, st, x, n,
+                     partial);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial,
                      kDotBlocks, out);
   return hipGetLastError();

@@ -59,6 +59,7 @@ struct Slot {
   float* ck = nullptr;       // [nseg][u | v][field] (checkpoint mode)
   float* segd2 = nullptr;    // [ckpt_k][nz][nx] (checkpoint mode)
   float* wav = nullptr;      // [nt_max]
+  float* illum = nullptr;    // [nz][nx] sum of squared Born sources (cache)
   int* rptr = nullptr;       // [ntiles_max + 1]
   int2* rent = nullptr;      // [nrec_max]
   int* rsidx = nullptr;      // [nrec_max]
@@ -107,6 +108,8 @@ struct brls_ctx {
   float* fields_all = nullptr;
   float *m = nullptr, *p = nullptr, *s = nullptr, *gbuf = nullptr,
         *born_in = nullptr;
+  int precond = 0;        // 1: diagonal illumination preconditioner
+  float *minv = nullptr, *z = nullptr;  // its inverse; preconditioned s
   double* acc = nullptr;
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr;
   double *partial = nullptr, *scal = nullptr;
@@ -457,8 +460,46 @@ int ensure_backgrounds(brls_ctx* c) {
                      0, wr, 1, n & 1)))
         return rc;
   }
+  // cache mode: each new shot's illumination (sum of its squared stored
+  // Born-source frames), for the preconditioner
+  if (!c->ckpt_k)
+    for (int i : todo) {
+      const Slot& sl = c->slots[i];
+      HIPCHECK(c, launch_sumsq_frames(sl.d2, std::max(sl.nt - 1, 0),
+                                      c->mplane, sl.illum, c->st));
+    }
   HIPCHECK(c, hipStreamSynchronize(c->st));
   for (int i : todo) c->slots[i].bg_ready = true;
+  return BRLS_OK;
+}
+
+// Stabiliser of the illumination preconditioner, relative to its mean.
+constexpr double kIllumEps = 0.01;
+
+int read_scalars(brls_ctx* c, double* out, int n);
+
+// Window illumination (sum over the window's slots) into out.
+int window_illumination(brls_ctx* c, float* out) {
+  int rc;
+  if ((rc = ensure_tab(c)) || (rc = ensure_backgrounds(c))) return rc;
+  HIPCHECK(c, launch_fill_f32(out, c->mplane, 0.f, c->st));
+  for (int i : c->order)
+    HIPCHECK(c, launch_axpy(out, c->slots[i].illum, 1.0, c->mplane, c->st));
+  return BRLS_OK;
+}
+
+// minv = 1 / (I + kIllumEps * mean(I)), I the window illumination.
+int build_minv(brls_ctx* c) {
+  int rc;
+  if ((rc = window_illumination(c, c->minv))) return rc;
+  HIPCHECK(c, launch_sum(c->minv, c->mplane, c->partial, c->scal, c->st));
+  double sum = 0.0;
+  if ((rc = read_scalars(c, &sum, 1))) return rc;
+  const double shift = kIllumEps * sum / (double)c->mplane;
+  if (!(shift > 0.0))
+    return fail(c, BRLS_EBREAKDOWN,
+                "preconditioner: the window's shots illuminate nothing");
+  HIPCHECK(c, launch_recip_shift(c->minv, c->minv, shift, c->mplane, c->st));
   return BRLS_OK;
 }
 
@@ -785,6 +826,8 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   ALLOC(c->s, mpts);
   ALLOC(c->gbuf, mpts);
   ALLOC(c->born_in, mpts);
+  ALLOC(c->minv, mpts);
+  ALLOC(c->z, mpts);
   ALLOC(c->acc, (int64_t)g.q_max * mpts);
   ALLOC(c->dobs, (int64_t)g.q_max * c->seg);
   ALLOC(c->r, (int64_t)g.q_max * c->seg);
@@ -808,6 +851,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
       ALLOC(sl.segd2, (int64_t)c->ckpt_k * mpts);
     } else {
       ALLOC(sl.d2, (int64_t)(g.nt_max - 1) * mpts);
+      ALLOC(sl.illum, mpts);
     }
     ALLOC(sl.wav, g.nt_max);
     ALLOC(sl.rptr, c->ntiles_max + 1);
@@ -1035,11 +1079,22 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
     ref = std::sqrt(sc[0]);
     st.ref_norm = ref;
   }
-  HIPCHECK(c, hipMemcpyAsync(c->p, c->s, M * 4, hipMemcpyDeviceToDevice,
-                             c->st));
+  // preconditioned form (diagonal illumination): directions follow
+  // z = M^{-1} s and gamma = <s, z>; the stop test stays on ||s||
+  double snorm = std::sqrt(gamma);
+  const bool pre = c->precond != 0;
+  if (pre) {
+    if ((rc = build_minv(c))) return finish(rc);
+    HIPCHECK(c, launch_mul(c->z, c->minv, c->s, M, c->st));
+    HIPCHECK(c, launch_dot(c->s, c->z, M, c->partial, c->scal, c->st));
+    if ((rc = read_scalars(c, sc, 1))) return finish(rc);
+    gamma = sc[0];
+  }
+  HIPCHECK(c, hipMemcpyAsync(c->p, pre ? c->z : c->s, M * 4,
+                             hipMemcpyDeviceToDevice, c->st));
   for (int it = 0; it < max_iter; ++it) {
     if (gamma == 0.0) break;
-    if (rtol > 0 && std::sqrt(gamma) <= rtol * ref) break;
+    if (rtol > 0 && snorm <= rtol * ref) break;
     if ((rc = born_of(c, c->p))) return finish(rc);
     HIPCHECK(c, launch_dot(c->q, c->q, D, c->partial, c->scal, c->st));
     HIPCHECK(c, launch_dot(c->p, c->p, M, c->partial, c->scal + 1, c->st));
@@ -1056,15 +1111,20 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
     if ((rc = adjoint_of(c, c->r))) return finish(rc);
     HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, c->m, lam, M, c->partial,
                                  c->scal, c->st));
-    if ((rc = read_scalars(c, sc, 1))) return finish(rc);
-    const double gnew = sc[0];
-    if (!std::isfinite(gnew))
+    if (pre) {
+      HIPCHECK(c, launch_mul(c->z, c->minv, c->s, M, c->st));
+      HIPCHECK(c, launch_dot(c->s, c->z, M, c->partial, c->scal + 1, c->st));
+    }
+    if ((rc = read_scalars(c, sc, pre ? 2 : 1))) return finish(rc);
+    const double gnew = pre ? sc[1] : sc[0];
+    if (!std::isfinite(sc[0]) || !std::isfinite(gnew))
       return finish(fail(c, BRLS_ENONFINITE, "non-finite gradient norm"));
     const double beta = gnew / gamma;
-    HIPCHECK(c, launch_xpby(c->p, c->s, beta, M, c->st));
+    HIPCHECK(c, launch_xpby(c->p, pre ? c->z : c->s, beta, M, c->st));
     gamma = gnew;
+    snorm = std::sqrt(sc[0]);
     st.iters = it + 1;
-    st.s_norm = std::sqrt(gamma);
+    st.s_norm = snorm;
   }
   HIPCHECK(c, launch_dot(c->r, c->r, D, c->partial, c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
@@ -1075,6 +1135,37 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
 int brls_image(brls_ctx* c, float* out) {
   if (!c || !out) return fail(c, BRLS_EINVAL, "NULL argument");
   HIPCHECK(c, hipMemcpyAsync(out, c->m, c->mplane * 4, out_kind(c), c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_set_precond(brls_ctx* c, int32_t mode) {
+  if (!c) return BRLS_EINVAL;
+  if (mode != 0 && mode != 1)
+    return fail(c, BRLS_EINVAL, "preconditioner mode %d unknown", mode);
+  if (mode == 1 && c->ckpt_k)
+    return fail(c, BRLS_EINVAL,
+                "the illumination preconditioner needs stored Born sources "
+                "(checkpoint interval 0)");
+  c->precond = mode;
+  return BRLS_OK;
+}
+
+int brls_get_precond(const brls_ctx* c, int32_t* mode) {
+  if (!c || !mode) return BRLS_EINVAL;
+  *mode = c->precond;
+  return BRLS_OK;
+}
+
+int brls_illumination(brls_ctx* c, float* out) {
+  if (!c || !out) return fail(c, BRLS_EINVAL, "NULL argument");
+  if (c->ckpt_k)
+    return fail(c, BRLS_EINVAL,
+                "the illumination needs stored Born sources (checkpoint "
+                "interval 0)");
+  int rc;
+  if ((rc = window_illumination(c, c->gbuf))) return rc;
+  HIPCHECK(c, hipMemcpyAsync(out, c->gbuf, c->mplane * 4, out_kind(c), c->st));
   HIPCHECK(c, hipStreamSynchronize(c->st));
   return BRLS_OK;
 }

@@ -79,6 +79,18 @@ hipError_t launch_sub(float* r, const float* d, const float* q, int64_t n,
 hipError_t launch_grad_norm(float* s, const float* g, const float* m,
                             double lambda, int64_t n, double* partial,
                             double* out, hipStream_t st);
+// out[i] = sum_f x[f][i]^2 over nframes frames of n floats (float64 sums)
+hipError_t launch_sumsq_frames(const float* x, int64_t nframes, int64_t n,
+                               float* out, hipStream_t st);
+// z = a * b elementwise
+hipError_t launch_mul(float* z, const float* a, const float* b, int64_t n,
+                      hipStream_t st);
+// y = 1 / (x + shift) (float64 arithmetic; y may alias x)
+hipError_t launch_recip_shift(float* y, const float* x, double shift,
+                              int64_t n, hipStream_t st);
+// partial sums, then out[0] = sum(x) (float64, fixed order)
+hipError_t launch_sum(const float* x, int64_t n, double* partial, double* out,
+                      hipStream_t st);
 // flag[0] = 1 if any entry of x is NaN or Inf (flag must start at 0)
 hipError_t launch_nonfinite(const float* x, int64_t n, int* flag,
                             hipStream_t st);

@@ -455,3 +455,63 @@ def test_streaming_chain_matches_oracle(P, mode):
     img = _gpu_chain(ctx, w, data, w.niter)
     ctx.close()
     assert rel(img, ref.m) <= IMG_TOL
+
+
+# --- preconditioned window CG --------------------------------------------
+
+def test_illumination_matches_oracle(P):
+    import oracle
+    w = synth.layers2d_64x64()
+    idx = [0, 1]
+    ctx = open_ctx(w, q_max=2)
+    for i in idx:
+        add_shot(ctx, w, i)
+    got = ctx.illumination()
+    want = oracle.illumination(oracle_problem(w), idx)
+    ctx.close()
+    assert rel(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_preconditioned_solve_matches_oracle(P, mode):
+    """The first window of the 64 x 64 chain, 10 iterations of CG
+    preconditioned by the window's illumination, with the bench's launch
+    choice: image and final residual norms vs the oracle's PCG."""
+    import oracle
+    w = synth.layers2d_64x64()
+    prob, data, lam = _chain_inputs(w, 0)
+    idx = w.windows()[0]
+    minv = oracle.illumination_minv(oracle.illumination(prob, idx))
+    ref = oracle.cgls(prob, idx, [data[i].astype(np.float64) for i in idx],
+                      lam, w.niter, minv=minv)
+    plain = oracle.cgls(prob, idx, [data[i].astype(np.float64) for i in idx],
+                        lam, w.niter)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    ctx.set_tuning(*_bench_tuning())
+    ctx.set_exec(mode)
+    ctx.set_precond(1)
+    assert ctx.get_precond() == 1
+    for i in idx:
+        add_shot(ctx, w, i, data[i])
+    st = ctx.solve_window(w.niter)
+    img = ctx.image()
+    ctx.close()
+    print(f"PCG vs CG after {w.niter} iterations: ||s|| "
+          f"{ref.s_norms[-1]:.4e} vs {plain.s_norms[-1]:.4e}")
+    assert st["iters"] == w.niter
+    assert rel(img, ref.m) <= IMG_TOL
+    assert abs(st["s_norm"] - ref.s_norms[-1]) <= 1e-3 * ref.s_norms[-1]
+    assert rel(img, plain.m) > 10 * IMG_TOL  # it is a different iteration
+
+
+def test_preconditioner_needs_stored_sources(P):
+    w = synth.layers2d_64x64()
+    ctx = open_ctx(w, q_max=2, ckpt_interval=-1)
+    with pytest.raises(P.BrlsError) as e:
+        ctx.set_precond(1)
+    assert e.value.code == -1 and "stored" in str(e.value)
+    with pytest.raises(P.BrlsError):
+        ctx.illumination()
+    with pytest.raises(P.BrlsError):
+        ctx.set_precond(2)
+    ctx.close()
