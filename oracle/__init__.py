@@ -258,7 +258,8 @@ class CGLSResult:
 def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
          lam: float, niter: int, m0: Optional[np.ndarray] = None,
          rtol: float = 0.0, keep_iterates: bool = False,
-         minv: Optional[np.ndarray] = None) -> CGLSResult:
+         minv: Optional[np.ndarray] = None,
+         m_ref: Optional[np.ndarray] = None) -> CGLSResult:
     """CG on min ||A m - d||^2 + lam ||m||^2 (eq. 3 / eq. 10), least-squares
     form: one A and one A^T per iteration, all in FP64.
 
@@ -267,6 +268,11 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
     (A^T A + lam I) m = A^T d: the search direction follows M^{-1} s, with
     gamma = <s, M^{-1} s>.
 
+    With ``m_ref`` the damping pulls towards m_ref instead of zero:
+    min ||A m - d||^2 + lam ||m - m_ref||^2, i.e. s = A^T r - lam (m - m_ref)
+    (the correction-regularised recursion when m_ref is the previous
+    window's image).
+
     Stops after ``niter`` iterations, or earlier once
     ||A^T r - lam m|| <= rtol * ||A^T d|| (s unpreconditioned in both)."""
     m = np.zeros(prob.grid.model_shape) if m0 is None else np.array(
@@ -274,9 +280,11 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
     d = [np.asarray(x, dtype=np.float64) for x in d]
     w = None if minv is None else np.asarray(
         minv, dtype=np.float64).reshape(prob.grid.model_shape)
+    mr = np.zeros(prob.grid.model_shape) if m_ref is None else np.array(
+        m_ref, dtype=np.float64).reshape(prob.grid.model_shape)
     Am = prob.born(m, idx)
     r = [di - ai for di, ai in zip(d, Am)]
-    s = prob.adjoint(r, idx) - lam * m
+    s = prob.adjoint(r, idx) - lam * (m - mr)
     z = s if w is None else w * s
     p = z.copy()
     gamma = float(np.vdot(s, z))
@@ -298,7 +306,7 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
         alpha = gamma / delta
         m = m + alpha * p
         r = [ri - alpha * qi for ri, qi in zip(r, q)]
-        s = prob.adjoint(r, idx) - lam * m
+        s = prob.adjoint(r, idx) - lam * (m - mr)
         z = s if w is None else w * s
         gamma_new = float(np.vdot(s, z))
         beta = gamma_new / gamma
@@ -346,13 +354,17 @@ class ChainResult:
 
 
 def chain(prob: Problem, data: Sequence[np.ndarray], windows, lam: float,
-          niter: int, m0: Optional[np.ndarray] = None) -> ChainResult:
+          niter: int, m0: Optional[np.ndarray] = None,
+          correction: bool = False) -> ChainResult:
     """Block-row recursion (eqs. 10-11): solve each window's damped problem by
-    CG, starting from the previous window's image (zero for the first)."""
+    CG, starting from the previous window's image (zero for the first).
+    ``correction``: damp the correction to the previous image instead of the
+    image (min ||A_w m - d_w||^2 + lam ||m - m_{w-1}||^2)."""
     m = m0
     images, results = [], []
     for w in windows:
-        res = cgls(prob, w, [data[i] for i in w], lam, niter, m0=m)
+        res = cgls(prob, w, [data[i] for i in w], lam, niter, m0=m,
+                   m_ref=m if correction else None)
         m = res.m
         images.append(m.copy())
         results.append(res)

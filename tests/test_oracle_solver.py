@@ -265,3 +265,59 @@ def test_illumination_from_recorded_background(orc):
     got = orc.illumination(prob, [0, 1]).ravel()
     assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
     assert np.all(got >= 0)
+
+
+# --- correction-regularised recursion ------------------------------------
+
+def test_correction_regularised_window_closed_form(orc, dense_problem):
+    """min ||A m - d||^2 + lam ||m - m_prev||^2 converges to
+    (A^T A + lam I)^-1 (A^T d + lam m_prev)."""
+    dp = dense_problem
+    idx = [0, 1]
+    A, d, H, b = _normal(dp, idx)
+    m_prev = synth.gaussian(dp["M"], 8) * 0.05
+    exact = np.linalg.solve(H, b + dp["lam"] * m_prev)
+    res = orc.cgls(dp["prob"], idx, [dp["data"][i] for i in idx], dp["lam"],
+                   150, m0=m_prev.reshape(dp["prob"].grid.model_shape),
+                   m_ref=m_prev.reshape(dp["prob"].grid.model_shape))
+    assert np.linalg.norm(res.m.ravel() - exact) <= 1e-9 * np.linalg.norm(
+        exact)
+
+
+def test_correction_regularised_iterates_are_cg_on_the_correction(
+        orc, dense_problem):
+    """From m_prev, the iterates are m_prev + the textbook-CG iterates of
+    (A^T A + lam I) delta = A^T (d - A m_prev)."""
+    dp = dense_problem
+    idx = [1, 2]
+    A, d, H, b = _normal(dp, idx)
+    m_prev = synth.gaussian(dp["M"], 9) * 0.05
+    ref = _textbook_cg(H, A.T @ (d - A @ m_prev), np.zeros(dp["M"]), 7)
+    shp = dp["prob"].grid.model_shape
+    res = orc.cgls(dp["prob"], idx, [dp["data"][i] for i in idx], dp["lam"],
+                   7, m0=m_prev.reshape(shp), m_ref=m_prev.reshape(shp),
+                   keep_iterates=True)
+    for k, (xr, xo) in enumerate(zip(ref, res.iterates)):
+        want = m_prev + xr
+        rel = np.linalg.norm(xo.ravel() - want) / np.linalg.norm(want)
+        assert rel < 1e-10, (k, rel)
+
+
+def test_correction_chain_keeps_memory(orc, dense_problem):
+    """Converged, the correction-regularised chain depends on the windows
+    before (each window solution is pulled towards the last), unlike the
+    image-regularised chain whose converged window solution does not."""
+    dp = dense_problem
+    wins = [[0, 1], [1, 2]]
+    a = orc.chain(dp["prob"], dp["data"], wins, dp["lam"], 150,
+                  correction=True)
+    b = orc.chain(dp["prob"], dp["data"], [wins[1]], dp["lam"], 150,
+                  correction=True)
+    c = orc.chain(dp["prob"], dp["data"], wins, dp["lam"], 150)
+    A, d, H, rhs = _normal(dp, wins[1])
+    assert np.linalg.norm(c.m.ravel() - np.linalg.solve(H, rhs)) <= \
+        1e-9 * np.linalg.norm(rhs)
+    prev = a.images[0].ravel()
+    assert np.linalg.norm(a.m.ravel() - np.linalg.solve(
+        H, rhs + dp["lam"] * prev)) <= 1e-9 * np.linalg.norm(a.m)
+    assert np.linalg.norm(a.m - b.m) > 1e-3 * np.linalg.norm(b.m)
