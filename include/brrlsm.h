@@ -151,7 +151,10 @@ int brls_window_data_size(const brls_ctx* ctx, int64_t* n);
 /* Solve eq. 10 on the current window by CG on the least-squares form,
  * starting from the current image (eq. 11's warm start) and leaving the
  * result as the current image. Stops after max_iter iterations or once
- * ||A^T r - lambda m|| <= rtol * ||A^T d|| (rtol <= 0 disables this test).
+ * ||A^T r - lambda m|| <= rtol * ||A^T d|| (rtol <= 0 disables this test;
+ * with brls_set_regularization mode 1 the damping term is
+ * lambda (m - m_start); with brls_set_precond mode 1 the CG is
+ * preconditioned).
  * Vectors are float32; the CG scalars (alpha, beta, norms) are float64.
  * An empty window or a zero gradient returns at once with iters = 0.
  * stats may be NULL. Errors: BRLS_EBREAKDOWN, BRLS_ENONFINITE. */
@@ -173,6 +176,16 @@ int brls_set_image(brls_ctx* ctx, const float* m);
  * sources (ckpt_interval 0); otherwise BRLS_EINVAL. */
 int brls_set_precond(brls_ctx* ctx, int32_t mode);
 int brls_get_precond(const brls_ctx* ctx, int32_t* mode);
+
+/* What the damping term of brls_solve_window pulls towards. Mode 0
+ * (default): zero, i.e. each window solves eq. 10 as posed, whole image
+ * regularised, warm-started from the current image (eq. 11 read with
+ * eq. 10's lambda). Mode 1: the image the solve starts from (the previous
+ * window's): min ||A_w m - d_w||^2 + lambda ||m - m_prev||^2, the
+ * correction-regularised recursion, which keeps memory of earlier windows.
+ * Other modes: BRLS_EINVAL. */
+int brls_set_regularization(brls_ctx* ctx, int32_t mode);
+int brls_get_regularization(const brls_ctx* ctx, int32_t* mode);
 
 /* The window's illumination [nz][ny][nx]: at each model point the sum over
  * the window's shots and time levels n = 0 .. nt-2 of (D2 u0^n)^2, the

@@ -156,6 +156,21 @@ class Context:
 
     set_precond = brls_set_precond
 
+    def brls_set_regularization(self, mode: int):
+        """0: damp the image; 1: damp the correction to the image the solve
+        starts from (correction-regularised recursion)."""
+        self._check(L.lib().brls_set_regularization(self._h, int(mode)))
+
+    set_regularization = brls_set_regularization
+
+    def brls_get_regularization(self) -> int:
+        v = ctypes.c_int32()
+        self._check(L.lib().brls_get_regularization(self._h,
+                                                    ctypes.byref(v)))
+        return v.value
+
+    get_regularization = brls_get_regularization
+
     def brls_get_precond(self) -> int:
         v = ctypes.c_int32()
         self._check(L.lib().brls_get_precond(self._h, ctypes.byref(v)))

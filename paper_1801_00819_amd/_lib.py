@@ -85,6 +85,8 @@ SIGNATURES = [
     ("brls_image", _I32, [_VP, _VP]),
     ("brls_set_image", _I32, [_VP, _VP]),
     ("brls_set_precond", _I32, [_VP, _I32]),
+    ("brls_set_regularization", _I32, [_VP, _I32]),
+    ("brls_get_regularization", _I32, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_get_precond", _I32, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_illumination", _I32, [_VP, _VP]),
     ("brls_apply_born", _I32, [_VP, _VP, _VP]),

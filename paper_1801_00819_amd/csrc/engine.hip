@@ -110,6 +110,9 @@ struct brls_ctx {
         *born_in = nullptr;
   int precond = 0;        // 1: diagonal illumination preconditioner
   float *minv = nullptr, *z = nullptr;  // its inverse; preconditioned s
+  int regularize = 0;     // 0: damp the image; 1: damp the correction to
+                          // the image the solve starts from
+  float* dm = nullptr;    // that correction (mode 1)
   double* acc = nullptr;
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr;
   double *partial = nullptr, *scal = nullptr;
@@ -828,6 +831,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   ALLOC(c->born_in, mpts);
   ALLOC(c->minv, mpts);
   ALLOC(c->z, mpts);
+  ALLOC(c->dm, mpts);
   ALLOC(c->acc, (int64_t)g.q_max * mpts);
   ALLOC(c->dobs, (int64_t)g.q_max * c->seg);
   ALLOC(c->r, (int64_t)g.q_max * c->seg);
@@ -1061,9 +1065,13 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
   // r = d - A m
   if ((rc = born_of(c, c->m))) return finish(rc);
   HIPCHECK(c, launch_sub(c->r, c->dobs, c->q, D, c->st));
-  // s = A^T r - lambda m, gamma = ||s||^2
+  // s = A^T r - lambda m (correction mode: - lambda (m - m_start)),
+  // gamma = ||s||^2
+  const bool corr = c->regularize == 1;
+  if (corr) HIPCHECK(c, launch_fill_f32(c->dm, M, 0.f, c->st));
+  const float* damped = corr ? c->dm : c->m;
   if ((rc = adjoint_of(c, c->r))) return finish(rc);
-  HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, c->m, lam, M, c->partial,
+  HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                                c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
   double gamma = sc[0];
@@ -1107,9 +1115,10 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
                          delta));
     const double alpha = gamma / delta;
     HIPCHECK(c, launch_axpy(c->m, c->p, alpha, M, c->st));
+    if (corr) HIPCHECK(c, launch_axpy(c->dm, c->p, alpha, M, c->st));
     HIPCHECK(c, launch_axpy(c->r, c->q, -alpha, D, c->st));
     if ((rc = adjoint_of(c, c->r))) return finish(rc);
-    HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, c->m, lam, M, c->partial,
+    HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                                  c->scal, c->st));
     if (pre) {
       HIPCHECK(c, launch_mul(c->z, c->minv, c->s, M, c->st));
@@ -1148,6 +1157,20 @@ int brls_set_precond(brls_ctx* c, int32_t mode) {
                 "the illumination preconditioner needs stored Born sources "
                 "(checkpoint interval 0)");
   c->precond = mode;
+  return BRLS_OK;
+}
+
+int brls_set_regularization(brls_ctx* c, int32_t mode) {
+  if (!c) return BRLS_EINVAL;
+  if (mode != 0 && mode != 1)
+    return fail(c, BRLS_EINVAL, "regularisation mode %d unknown", mode);
+  c->regularize = mode;
+  return BRLS_OK;
+}
+
+int brls_get_regularization(const brls_ctx* c, int32_t* mode) {
+  if (!c || !mode) return BRLS_EINVAL;
+  *mode = c->regularize;
   return BRLS_OK;
 }
 

@@ -515,3 +515,26 @@ def test_preconditioner_needs_stored_sources(P):
     with pytest.raises(P.BrlsError):
         ctx.set_precond(2)
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_correction_regularised_chain_matches_oracle(P, mode):
+    """The 64 x 64 chain with the damping pulling towards the previous
+    window's image (correction-regularised recursion), bench launch choice,
+    vs the oracle's chain in the same mode."""
+    import oracle
+    w = synth.layers2d_64x64()
+    prob, data, lam = _chain_inputs(w, 0)
+    ref = oracle.chain(prob, [d.astype(np.float64) for d in data],
+                       w.windows(), lam, w.niter, correction=True)
+    plain = oracle.chain(prob, [d.astype(np.float64) for d in data],
+                         w.windows(), lam, w.niter)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    ctx.set_tuning(*_bench_tuning())
+    ctx.set_exec(mode)
+    ctx.set_regularization(1)
+    assert ctx.get_regularization() == 1
+    img = _gpu_chain(ctx, w, data, w.niter)
+    ctx.close()
+    assert rel(img, ref.m) <= IMG_TOL
+    assert rel(img, plain.m) > 10 * IMG_TOL
