@@ -464,7 +464,7 @@ def bench_stream(args, P, synth, torch):
         x += 0.01 * rms * torch.randn(x.shape, generator=gen, device="cuda")
     log(f"stream: data for {nsh} shots in {time.perf_counter() - t0:.1f}s")
 
-    def run(Q, exec_mode, nwin):
+    def run(Q, exec_mode, nwin, regularize=0):
         w = synth.stream2d_512x1024(nshots=nsh, Q=Q)
         wins = w.windows()[:nwin]
         c = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt_max, nrec_max, Q, w.h,
@@ -488,8 +488,12 @@ def bench_stream(args, P, synth, torch):
                         w.dt, w.lam_rel * nrm, vel, device=True)
         c.set_tuning(*DEFAULT_TUNING)
         c.set_exec(exec_mode)
+        c.set_regularization(regularize)
         image = torch.empty(w.model_shape, dtype=torch.float32, device="cuda")
-        held, lat, its = [], [], []
+        prev = torch.zeros_like(image)
+        m0 = torch.from_numpy(w.m_true).cuda()
+        drift = torch.from_numpy(w.extra["drift"]).cuda()
+        held, lat, its, err, chg = [], [], [], [], []
         for win in wins:
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -507,27 +511,51 @@ def bench_stream(args, P, synth, torch):
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - t)
             its.append(st["iters"])
+            # image quality, outside the timed latency: relative error
+            # against the model the window's middle shot sees, and the
+            # relative change from the previous window's image
+            truth = m0 + (win[len(win) // 2] / 64.0) * drift
+            img = image.double()
+            err.append(float(torch.linalg.vector_norm(img - truth)
+                             / torch.linalg.vector_norm(truth)))
+            chg.append(float(torch.linalg.vector_norm(img - prev)
+                             / torch.linalg.vector_norm(img)))
+            prev.copy_(image)
         c.close()
-        return lat, len(w.windows())
+        return lat, len(w.windows()), err, chg
 
-    per_q = {}
-    for Q in (4, 8, 16):
-        lat, total = run(Q, P.BRLS_EXEC_GRAPH, 10 ** 9)
-        plain, _ = run(Q, P.BRLS_EXEC_PLAIN, args.stream_plain_windows)
+    def summary(lat, err, chg):
         # the first window of each run includes graph capture and the
         # backgrounds of all Q shots; latencies are over the later windows
         steady = lat[1:] if len(lat) > 1 else lat
-        per_q[Q] = {
+        half = len(err) // 2
+        return {
             "windows": len(lat),
             "p50_s": round(float(np.percentile(steady, 50)), 4),
             "p99_s": round(float(np.percentile(steady, 99)), 4),
             "mean_s": round(float(np.mean(steady)), 4),
             "first_window_s": round(lat[0], 4),
-            "plain_windows": len(plain),
-            "plain_p50_s": round(float(np.percentile(plain[1:] or plain,
-                                                      50)), 4),
+            "image_rel_err_last": round(err[-1], 4),
+            "image_rel_err_mean_second_half": round(
+                float(np.mean(err[half:])), 4),
+            "image_rel_change_mean_second_half": round(
+                float(np.mean(chg[half:])), 4),
         }
+
+    per_q = {}
+    for Q in (4, 8, 16):
+        lat, total, err, chg = run(Q, P.BRLS_EXEC_GRAPH, 10 ** 9)
+        plain, _, _, _ = run(Q, P.BRLS_EXEC_PLAIN, args.stream_plain_windows)
+        per_q[Q] = summary(lat, err, chg)
+        per_q[Q]["plain_windows"] = len(plain)
+        per_q[Q]["plain_p50_s"] = round(
+            float(np.percentile(plain[1:] or plain, 50)), 4)
         log(f"stream Q={Q}: {per_q[Q]}")
+    # the correction-regularised recursion (damping towards the previous
+    # window's image instead of towards zero) on the same Q = 8 stream
+    lat, _, err, chg = run(8, P.BRLS_EXEC_GRAPH, 10 ** 9, regularize=1)
+    corr = summary(lat, err, chg)
+    log(f"stream Q=8 correction-regularised: {corr}")
     out = {
         "metric": "window solve latency p50 (Q=8)",
         "value": per_q[8]["p50_s"],
@@ -542,6 +570,7 @@ def bench_stream(args, P, synth, torch):
                                "iterations per window, drift 0.1 % per 64 "
                                "shots"},
         "per_window_size": {str(k): v for k, v in per_q.items()},
+        "correction_regularised_q8": corr,
     }
     print(json.dumps(out), flush=True)
 
