@@ -21,7 +21,10 @@ What it computes (Kazemi & Sacchi, arXiv 1801.00819):
     paper asks for in each window's CG (it names none; this build's reading:
     the source-side illumination sum over the window's shots and time levels
     of (D2 u0^n)^2, inverted with a stabiliser of 1 % of its mean), used by
-    ``cgls(..., minv=...)``.
+    ``cgls(..., minv=...)``;
+  * ``oracle.ssf``: the paper's own operator family, split-step Fourier
+    shot-profile de-migration and migration (Examples section), whose
+    problems plug into ``cgls`` and ``chain`` unchanged.
 """
 from __future__ import annotations
 
