@@ -65,6 +65,23 @@ class brls_kstat(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class brls_ssf_grid(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dz", ctypes.c_double),
+                ("nt", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("fmin", ctypes.c_double), ("fmax", ctypes.c_double),
+                ("ntap", ctypes.c_int32), ("nrec_max", ctypes.c_int32),
+                ("q_max", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+class brls_ssf_shot(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("xs", ctypes.c_int32),
+                ("nrec", ctypes.c_int32), ("f0", ctypes.c_double),
+                ("rec", ctypes.POINTER(ctypes.c_int32)),
+                ("data", ctypes.c_void_p)]
+
+
 # (name, restype, argtypes) of every exported symbol
 _VP = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -113,6 +130,30 @@ SIGNATURES = [
                                  ctypes.POINTER(_I32)]),
     ("brls_memory_bytes", _I32, [_VP, ctypes.POINTER(_I64)]),
     ("brls_sync", _I32, [_VP]),
+    # split-step Fourier context (include/brrlsm_ssf.h)
+    ("brls_ssf_open", _I32, [ctypes.POINTER(brls_ssf_grid), _VP, _VP,
+                             ctypes.POINTER(_VP)]),
+    ("brls_ssf_close", None, [_VP]),
+    ("brls_ssf_last_error", ctypes.c_char_p, [_VP]),
+    ("brls_ssf_band", _I32, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                             ctypes.POINTER(ctypes.c_double)]),
+    ("brls_ssf_update", _I32, [_VP, ctypes.POINTER(brls_ssf_shot)]),
+    ("brls_ssf_downdate", _I32, [_VP, _I64]),
+    ("brls_ssf_window", _I32, [_VP, ctypes.POINTER(_I64), _I32,
+                               ctypes.POINTER(_I32)]),
+    ("brls_ssf_window_data_size", _I32, [_VP, ctypes.POINTER(_I64)]),
+    ("brls_ssf_apply_born", _I32, [_VP, _VP, _VP]),
+    ("brls_ssf_apply_adjoint", _I32, [_VP, _VP, _VP]),
+    ("brls_ssf_observed", _I32, [_VP, _VP]),
+    ("brls_ssf_solve_window", _I32, [_VP, _I32, ctypes.c_double,
+                                     ctypes.POINTER(brls_stats)]),
+    ("brls_ssf_image", _I32, [_VP, _VP]),
+    ("brls_ssf_set_image", _I32, [_VP, _VP]),
+    ("brls_ssf_kernel_timing", _I32, [_VP, _I32]),
+    ("brls_ssf_kernel_stats", _I32, [_VP, ctypes.POINTER(brls_kstat), _I32,
+                                     ctypes.POINTER(_I32)]),
+    ("brls_ssf_memory_bytes", _I32, [_VP, ctypes.POINTER(_I64)]),
+    ("brls_ssf_sync", _I32, [_VP]),
 ]
 
 _lib = None
@@ -151,5 +192,12 @@ class BrlsError(RuntimeError):
 def check(rc: int, ctx=None):
     if rc != BRLS_OK:
         msg = lib().brls_last_error(ctx)
+        raise BrlsError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def check_ssf(rc: int, ctx=None):
+    if rc != BRLS_OK:
+        msg = lib().brls_ssf_last_error(ctx)
         raise BrlsError(rc, msg.decode() if msg else "")
     return rc

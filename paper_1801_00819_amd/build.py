@@ -2,12 +2,13 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbrrlsm.so")
 SOURCES = ["stencil2d.hip", "march2d.hip", "march2t.hip", "stencil3d.hip",
-           "blas.hip", "engine.hip"]
+           "blas.hip", "engine.hip", "ssf.hip", "ssf_engine.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed fp32 instructions (v_pk_*_f32) in generated code
@@ -16,12 +17,29 @@ FLAGS = [
 ]
 
 
+def _compile(hipcc, src, obj, verbose):
+    cmd = [hipcc] + FLAGS + ["-c", "-I", os.path.join(ROOT, "include"),
+                             "-I", os.path.join(HERE, "csrc"), "-o", obj, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel, then link."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
     srcs = [os.path.join(HERE, "csrc", s) for s in SOURCES]
+    objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o")
+            for s in SOURCES]
+    jobs = max(1, min(len(srcs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_compile, hipcc, s, o, verbose)
+                  for s, o in zip(srcs, objs)]:
+            f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I",
-                             os.path.join(HERE, "csrc"), "-o", tmp] + srcs
+    cmd = [hipcc] + FLAGS + ["-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -9,6 +9,10 @@ library and the CPU oracle implement those themselves.
 from .configs import (  # noqa: F401
     Workload,
     Shot,
+    SsfShot,
+    SsfWorkload,
+    ssf_small,
+    ssf2d_256x1024,
     layers2d_64x64,
     faulted2d_512x1024,
     layered3d_256x320x320,

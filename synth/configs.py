@@ -27,6 +27,8 @@ SEED_LAYERS2D_64 = 0
 SEED_FAULTED2D_512 = 1
 SEED_LAYERED3D_256 = 3
 SEED_STREAM2D_512 = 4
+SEED_SSF2D_256 = 5
+SEED_SSF_SMALL = 6
 
 
 def rng(seed_group: int, stream: int) -> np.random.Generator:
@@ -128,10 +130,10 @@ def layers2d_64x64() -> Workload:
                     15.0, vel, m, shots, Q=2, S=1, niter=10, lam_rel=0.01)
 
 
-def faulted_reflectivity(nz: int, nx: int, r_layers, r_faults,
-                         nlayers: int = 40, nfaults: int = 10) -> np.ndarray:
-    """Vertical derivative of a random layered model cut by dipping faults,
-    scaled to max |m| = 0.1."""
+def faulted_blocks(nz: int, nx: int, r_layers, r_faults,
+                   nlayers: int = 40, nfaults: int = 10) -> np.ndarray:
+    """A random layered model cut by dipping faults: piecewise-constant
+    values in [-1, 1]."""
     xc = (nx - 1) / 2.0
     depths = np.sort(r_layers.uniform(16, nz - 12, size=nlayers))
     dips = r_layers.uniform(-0.05, 0.05, size=nlayers)
@@ -155,6 +157,14 @@ def faulted_reflectivity(nz: int, nx: int, r_layers, r_faults,
     for i in range(nlayers):
         iface = depths[i] + dips[i] * (x - xc)
         b = np.where(zeff >= iface, values[i + 1], b)
+    return b
+
+
+def faulted_reflectivity(nz: int, nx: int, r_layers, r_faults,
+                         nlayers: int = 40, nfaults: int = 10) -> np.ndarray:
+    """Vertical derivative of a random layered model cut by dipping faults,
+    scaled to max |m| = 0.1."""
+    b = faulted_blocks(nz, nx, r_layers, r_faults, nlayers, nfaults)
     m = np.zeros((nz, nx))
     m[:-1] = b[1:] - b[:-1]
     mx = np.abs(m).max()
@@ -346,3 +356,111 @@ def unit_random_like(shape, seed: int, norm: Optional[float] = None):
     if norm is not None:
         v *= norm / np.linalg.norm(v)
     return v
+
+
+# ---------------------------------------------------------------------------
+# Split-step Fourier (shot-profile, one-way) workloads: 2-D models whose
+# lateral size is a power of two (the lateral FFT length, taper included),
+# sources and receivers on the top level.
+# ---------------------------------------------------------------------------
+@dataclass
+class SsfShot:
+    id: int
+    xs: int          # source column
+    rec: np.ndarray  # int32 [nrec] receiver columns
+    f0: float
+
+    @property
+    def nrec(self) -> int:
+        return int(self.rec.size)
+
+
+@dataclass
+class SsfWorkload:
+    name: str
+    seed_group: int
+    nz: int
+    nx: int
+    dx: float
+    dz: float
+    nt: int
+    dt: float
+    fmin: float
+    fmax: float
+    ntap: int
+    vel: np.ndarray     # float64 [nz, nx], m/s (the migration velocity)
+    m_true: np.ndarray  # float64 [nz, nx]
+    shots: List[SsfShot]
+    Q: int
+    S: int
+    niter: int
+    lam_rel: float
+    noise_rel: float = 0.01
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def model_shape(self):
+        return (self.nz, self.nx)
+
+    windows = Workload.windows
+
+
+def _smooth2(a: np.ndarray, half: int) -> np.ndarray:
+    """Box average over (2 half + 1)^2 cells, edges replicated."""
+    p = np.pad(a, half, mode="edge")
+    c = np.cumsum(np.cumsum(p, 0), 1)
+    c = np.pad(c, ((1, 0), (1, 0)))
+    k = 2 * half + 1
+    return (c[k:, k:] - c[:-k, k:] - c[k:, :-k] + c[:-k, :-k]) / (k * k)
+
+
+def ssf_small(nz: int = 24, nx: int = 64, nt: int = 256, dt: float = 4e-3,
+              fmin: float = 4.0, fmax: float = 40.0, ntap: int = 8,
+              seed: int = 0) -> SsfWorkload:
+    """Small split-step case for parity: v rising with depth plus a lateral
+    sine and seeded noise, a random reflectivity, three shots with
+    different receiver sets (a dense split spread, a scattered set with both
+    edge columns and a repeated column, an off-end spread to the left)."""
+    r = rng(SEED_SSF_SMALL, seed)
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    vel = 1700.0 + 1200.0 * z / max(nz - 1, 1) + 180.0 * np.sin(
+        2 * np.pi * x / nx + 2.0 * z / max(nz, 1))
+    vel += 40.0 * r.standard_normal((nz, nx))
+    m = 0.1 * r.standard_normal((nz, nx))
+    xs = [nx // 3, nx // 2 + 1, (5 * nx) // 6]
+    recs = [np.arange(nx // 8, nx - nx // 16, 2),
+            np.array([0, 5, 5, nx // 4 + 1, nx - 1, (5 * nx) // 8]),
+            np.array([xs[2] - 4 - 2 * k for k in range(12)])]
+    shots = [SsfShot(i, xs[i], recs[i].astype(np.int32), 15.0)
+             for i in range(3)]
+    return SsfWorkload("ssf-small-%dx%d" % (nz, nx), SEED_SSF_SMALL, nz, nx,
+                       10.0, 10.0, nt, dt, fmin, fmax, ntap, vel, m, shots,
+                       Q=2, S=1, niter=5, lam_rel=1e-2)
+
+
+def ssf2d_256x1024(nshots: int = 240) -> SsfWorkload:
+    """Stand-in for the paper's Marmousi example (Examples section): 2-D,
+    256 x 1024 at 12.5 m (3.2 x 12.8 km, 32-cell tapers at the sides), a
+    faulted layered velocity 1500 -> 4500 m/s smoothed over 9 cells as the
+    migration velocity, faulted layered reflectivity; 240 shots 25 m apart
+    (the paper's count and spacing), each with 96 receivers 25 m apart on an
+    off-end spread to the left of the source (near offset 100 m), 20 Hz
+    Ricker, 4096 samples at 1 ms, band 3-40 Hz (151 frequencies); windows of
+    5 shots sliding by 3, 8 CG iterations (the paper's configuration)."""
+    nz, nx, h = 256, 1024, 12.5
+    b = faulted_blocks(nz, nx, rng(SEED_SSF2D_256, 0), rng(SEED_SSF2D_256, 3))
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    vtrue = 1500.0 + 2600.0 * (z / (nz - 1)) ** 0.8 + 400.0 * b * (
+        0.3 + 0.7 * z / (nz - 1))
+    vel = _smooth2(vtrue, 4)
+    m = faulted_reflectivity(nz, nx, rng(SEED_SSF2D_256, 0),
+                             rng(SEED_SSF2D_256, 3))
+    shots = []
+    for i in range(nshots):
+        xs = 300 + 2 * i
+        rec = np.array([xs - 8 - 2 * k for k in range(96)], dtype=np.int32)
+        shots.append(SsfShot(i, xs, rec, 20.0))
+    return SsfWorkload("ssf2d-256x1024", SEED_SSF2D_256, nz, nx, h, h, 4096,
+                       1e-3, 3.0, 40.0, 32, vel, m, shots, Q=5, S=3, niter=8,
+                       lam_rel=1e-3, extra={"vel_true": vtrue})

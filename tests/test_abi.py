@@ -1,5 +1,5 @@
-"""The C-ABI library loads and exports every symbol include/brrlsm.h declares
-(no compute: this runs without a GPU)."""
+"""The C-ABI library loads and exports every symbol include/*.h declare (no
+compute: this runs without a GPU)."""
 import os
 import re
 
@@ -9,9 +9,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "brrlsm.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(brls_[a-z_0-9]+)\s*\(", src)))
+    inc = os.path.join(ROOT, "include")
+    names = set()
+    for f in sorted(os.listdir(inc)):
+        if not f.endswith(".h"):
+            continue
+        src = open(os.path.join(inc, f)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(brls_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_verbs():
@@ -52,3 +58,34 @@ def test_missing_library_fails_loudly(tmp_path):
             _lib.lib(str(tmp_path / "nope.so"))
     finally:
         _lib._lib = saved
+
+
+def test_split_step_header_declares_its_verbs():
+    names = _declared()
+    for verb in ("brls_ssf_open", "brls_ssf_update", "brls_ssf_downdate",
+                 "brls_ssf_solve_window", "brls_ssf_apply_born",
+                 "brls_ssf_apply_adjoint", "brls_ssf_image",
+                 "brls_ssf_close", "brls_ssf_last_error"):
+        assert verb in names
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=96), "power of two"),
+    (dict(nx=4096), "power of two"),
+    (dict(ntap=32), "ntap"),
+    (dict(fmin=60.0, fmax=50.0), "band"),
+    (dict(fmax=200.0), "band"),
+    (dict(fmin=20.1, fmax=20.2), "no DFT frequency"),
+    (dict(q_max=0), "q_max"),
+])
+def test_split_step_open_rejects_bad_grids(kw, msg):
+    import numpy as np
+    from paper_1801_00819_amd import BrlsError
+    from paper_1801_00819_amd.ssf import brls_ssf_open
+    a = dict(nz=8, nx=64, dx=10.0, dz=10.0, nt=256, dt=4e-3, fmin=4.0,
+             fmax=40.0, ntap=8, nrec_max=8, q_max=2, lam=0.0)
+    a.update(kw)
+    with pytest.raises(BrlsError) as e:
+        brls_ssf_open(**a, vel=np.full((a["nz"], a["nx"]), 2000.0,
+                                       np.float32))
+    assert e.value.code == -1 and msg in str(e.value)
