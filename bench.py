@@ -106,11 +106,15 @@ def parse():
     ap.add_argument("--only-steps", action="store_true",
                     help="time the steps only (for profiler runs)")
     ap.add_argument("--workload", default="2d",
-                    choices=["2d", "3d", "autograd", "stream"],
+                    choices=["2d", "3d", "autograd", "stream", "ssf"],
                     help="2d: the window chain (default); 3d: the batched "
                          "3-D operator pair; autograd: differentiable Born "
                          "with checkpointed backgrounds; stream: ragged "
-                         "streaming windows, latency p50/p99")
+                         "streaming windows, latency p50/p99; ssf: the "
+                         "split-step Fourier operator pair in the paper's "
+                         "window configuration")
+    ap.add_argument("--ssf-windows", type=int, default=0,
+                    help="ssf workload: windows of the chain to run (0: all)")
     ap.add_argument("--ops-only", action="store_true",
                     help="after setup run one 512 MiB device copy (the "
                          "counter calibration kernel) and one batched Born "
@@ -575,6 +579,268 @@ def bench_stream(args, P, synth, torch):
     print(json.dumps(out), flush=True)
 
 
+def ssf_flops_per_step(n):
+    """Algorithmic float operations of one depth step of one (shot,
+    frequency) field of n points: an n-point FFT and its inverse at
+    5 n log2 n each (the standard count), the wavenumber-domain phase and
+    the split-step phase with the taper (a complex multiply and a real
+    scale each: 8 per point), and the Born injection or imaging term (4 per
+    point). The phase angles' sine, cosine and square root are not
+    counted."""
+    return 10 * n * int(round(np.log2(n))) + 20 * n
+
+
+def ssf_bytes(kind, items, nz, n, nrec_items):
+    """Minimum HBM bytes of one launch over `items` (shot, frequency) pairs:
+    the Born weights of every item and level (8 B per point); Born: the
+    model once (4 B per point) and the receiver samples written (8 B per
+    complex sample); adjoint: the receiver samples read and every item's
+    image contribution written (4 B per point and level)."""
+    wb = items * nz * n * 8
+    if kind == "born":
+        return wb + nz * n * 4 + 8 * nrec_items
+    return wb + 8 * nrec_items + items * nz * n * 4
+
+
+def bench_ssf(args, P, synth, torch):
+    """Split-step Fourier shot-profile operator pair (the paper's own
+    operator family) in the paper's window configuration on the 256 x 1024
+    Marmousi stand-in: 240 shots, windows of 5 sliding by 3, 8 CG
+    iterations per window, warm-started. The observed data are two-way
+    finite-difference Born data of the same reflectivity (the library's
+    8th-order operator, sources and receivers 2 cells below the top of a
+    grid two rows taller), plus 1 % noise: the one-way operator never sees
+    its own modelling. Reports the chain's throughput, seconds per window,
+    per-kernel timing and the roofline of the dominant kernel."""
+    from paper_1801_00819_amd.ssf import brls_ssf_open
+    w = synth.ssf2d_256x1024()
+    nz, nx, Q = w.nz, w.nx, w.Q
+    nrec = w.shots[0].nrec
+    if args.ops_only:
+        # one 512 MiB device copy (calibrates the memory counters), then one
+        # Born and one adjoint application over the first window
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        c = brls_ssf_open(nz, nx, w.dx, w.dz, w.nt, w.dt, w.fmin, w.fmax,
+                          w.ntap, nrec, Q, 1.0, w.vel.astype(np.float32),
+                          device=True)
+        for i in w.windows()[0]:
+            s = w.shots[i]
+            c.update(i, s.xs, s.rec, s.f0)
+        m = torch.from_numpy(w.m_true.astype(np.float32)).cuda()
+        c.apply_adjoint(c.apply_born(m))
+        torch.cuda.synchronize()
+        c.close()
+        log("ssf ops-only: done")
+        return
+    windows = w.windows()
+    if args.ssf_windows > 0:
+        windows = windows[:args.ssf_windows]
+    need = sorted({i for win in windows for i in win})
+    # ---- two-way FD Born data (untimed) --------------------------------
+    t0 = time.perf_counter()
+    vel_fd = np.concatenate([np.repeat(w.vel[:1], 2, 0), w.vel], 0)
+    m_fd = np.concatenate([np.zeros((2, nx)), w.m_true], 0)
+    fd = P.brls_open(2, nz + 2, 1, nx, 40, w.nt, nrec, 8, w.dx, w.dt, 0.0,
+                     vel_fd[:, None, :].astype(np.float32), device=True)
+    fd.set_tuning(*DEFAULT_TUNING)
+    m_fd_t = torch.from_numpy(m_fd[:, None, :].astype(np.float32)).cuda()
+    data = {}
+    for b in range(0, len(need), 8):
+        ids = need[b:b + 8]
+        for i in ids:
+            s = w.shots[i]
+            rec = np.stack([np.full(nrec, 2), np.zeros(nrec, int), s.rec],
+                           1).astype(np.int32)
+            fd.update(i, (2, 0, s.xs), rec, w.nt, s.f0, None)
+        d = fd.apply_born(m_fd_t).view(len(ids), w.nt, nrec)
+        for k, i in enumerate(fd.window()):
+            data[i] = d[k].clone()
+        for i in ids:
+            fd.downdate(i)
+    fd.close()
+    rms = float(np.sqrt(sum(float((x.double() ** 2).sum())
+                            for x in data.values())
+                        / sum(x.numel() for x in data.values())))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5001)
+    for i in need:
+        data[i] += 0.01 * rms * torch.randn(data[i].shape, generator=gen,
+                                            device="cuda")
+    log(f"ssf: FD Born data for {len(need)} shots in "
+        f"{time.perf_counter() - t0:.1f}s")
+
+    def open_ctx(lam):
+        return brls_ssf_open(nz, nx, w.dx, w.dz, w.nt, w.dt, w.fmin, w.fmax,
+                             w.ntap, nrec, Q, lam, w.vel.astype(np.float32),
+                             device=True)
+
+    # ---- lambda: 1e-3 of ||A^T A|| on the first window (4 power steps) ----
+    c = open_ctx(0.0)
+    for i in windows[0]:
+        s = w.shots[i]
+        c.update(i, s.xs, s.rec, s.f0, data[i])
+    x = torch.from_numpy(synth.gaussian(w.model_shape, 5002)
+                         .astype(np.float32)).cuda()
+    x /= torch.linalg.vector_norm(x)
+    nrm = 0.0
+    for _ in range(4):
+        y = c.apply_adjoint(c.apply_born(x))
+        nrm = float(torch.linalg.vector_norm(y.double()))
+        x = y / nrm
+    k0, nw, df = c.band()
+    c.close()
+    lam = w.lam_rel * nrm
+    # ---- the chain (timed) ---------------------------------------------
+    c = open_ctx(lam)
+    image = torch.empty(w.model_shape, dtype=torch.float32, device="cuda")
+    held, lat, its = [], [], []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for win in windows:
+        t = time.perf_counter()
+        for i in list(held):
+            if i not in win:
+                c.downdate(i)
+                held.remove(i)
+        for i in win:
+            if i not in held:
+                s = w.shots[i]
+                c.update(i, s.xs, s.rec, s.f0, data[i])
+                held.append(i)
+        st = c.solve_window(w.niter)
+        c.image(image)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+        its.append(st["iters"])
+    total = time.perf_counter() - t_all
+    last = st
+    # migration image of the last window (A^T d), for the quality figure
+    mig = c.apply_adjoint(c.observed())
+    # ---- per-kernel timing on the last window ---------------------------
+    c.kernel_timing(True)
+    c.solve_window(2)
+    ks = c.kernel_stats()
+    c.kernel_timing(False)
+    mem = c.memory_bytes()
+    c.close()
+    items = Q * nw
+    nrec_items = items * nrec
+    roof = {}
+    for kind, name in (("born", "ssf_born"), ("adjoint", "ssf_adjoint")):
+        n, ms = ks[name]
+        avg = ms / n / 1e3
+        fl = items * (nz - 1) * ssf_flops_per_step(nx)
+        by = ssf_bytes(kind, items, nz, nx, nrec_items)
+        roof[kind] = dict(avg_us=avg * 1e6, flops=fl, bytes=by,
+                          tflops=fl / avg / 1e12, gbs=by / avg / 1e9)
+    n, ms = ks["ssf_image_sum"]
+    sum_us = ms / n * 1e3
+    sum_bytes = items * nz * nx * 4 + nz * nx * 4
+    dom = max(roof, key=lambda k: roof[k]["avg_us"])
+    # operator point-steps of the chain: every window runs niter + 1 Born
+    # and niter + 1 adjoint applications over its items x nz x nx points
+    pts = sum((it + 1) * 2 for it in its) * items * nz * nx
+    # quality: normalised correlation with the reflectivity in the zone the
+    # last window illuminates (from its leftmost receiver to its rightmost
+    # source), the chain's image against that window's migration image
+    lw = [w.shots[i] for i in windows[-1]]
+    zs = slice(16, nz - 16)
+    xs_ = slice(int(min(s.rec.min() for s in lw)),
+                int(max(s.xs for s in lw)) + 1)
+    mt = torch.from_numpy(w.m_true).cuda()
+
+    def corr(a):
+        a = a[zs, xs_].double()
+        b = mt[zs, xs_]
+        return float(torch.sum(a * b) / torch.linalg.vector_norm(a)
+                     / torch.linalg.vector_norm(b))
+    out = {
+        "metric": "split-step Born+adjoint Gpt-steps/s",
+        "value": round(pts / total / 1e9, 3),
+        "unit": "Gpt-steps/s",
+        "n_gpus": 1,
+        "steps": len(windows),
+        "warmup": 0,
+        "ms_per_step": round(float(np.mean(lat)) * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ssf2d-256x1024 (Marmousi stand-in): "
+                               f"{len(windows)} windows of 5 shots sliding "
+                               f"by 3 over {len(need)} shots, 96 receivers, "
+                               f"{nw} frequencies {w.fmin}-{w.fmax} Hz, 8 CG "
+                               "iterations, two-way FD Born data + 1 % "
+                               "noise",
+                   "model": [nz, nx]},
+        "s_per_window": {"mean": round(float(np.mean(lat)), 4),
+                         "p50": round(float(np.percentile(lat, 50)), 4),
+                         "max": round(float(np.max(lat)), 4),
+                         "chain_total_s": round(total, 3)},
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"{dom} (k_ssf_{dom})",
+            "achieved": round(roof[dom]["tflops"], 2),
+            "peak": 157.3,
+            "unit": "TFLOP/s",
+            "frac": round(roof[dom]["tflops"] / 157.3, 4),
+            "traffic": None,
+            "avg_launch_us": round(roof[dom]["avg_us"], 1),
+            "algorithmic_flops_per_launch": roof[dom]["flops"],
+            "hbm": {"algorithmic_bytes_per_launch": roof[dom]["bytes"],
+                    "achieved_GBs": round(roof[dom]["gbs"], 1)},
+            "other": {k: {"avg_launch_us": round(v["avg_us"], 1),
+                          "achieved_TFLOPs": round(v["tflops"], 2),
+                          "achieved_GBs": round(v["gbs"], 1)}
+                      for k, v in roof.items() if k != dom},
+            "image_sum": {"avg_launch_us": round(sum_us, 1),
+                          "achieved_GBs": round(sum_bytes / sum_us / 1e3,
+                                                1)},
+        },
+        "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3,
+                                                          1)}
+                    for k, v in ks.items()},
+        "quality": {"final_s_over_s0": round(last["s_norm"]
+                                             / last["s0_norm"], 4),
+                    "final_r_norm": last["r_norm"],
+                    "corr_chain_image": round(corr(image), 4),
+                    "corr_last_window_migration": round(corr(mig), 4),
+                    "zone_columns": [xs_.start, xs_.stop]},
+        "device_bytes": mem,
+    }
+    log(f"ssf: {len(windows)} windows in {total:.2f}s; kernels {ks}")
+    if not args.no_cpu_baseline:
+        from oracle.ssf import SsfProblem, SsfShot
+        nf = 16
+        s0 = w.shots[0]
+        prob = SsfProblem(w.vel.astype(np.float32).astype(np.float64), w.dx,
+                          w.dz, w.nt, w.dt, (k0 - 0.25) * df,
+                          (k0 + nf - 0.75) * df, w.ntap,
+                          [SsfShot(s0.xs, s0.rec, s0.f0)])
+        m64 = w.m_true.astype(np.float32).astype(np.float64)
+        W = prob.weights(0)
+        t = time.perf_counter()
+        D = prob.born_shot(0, m64, W)
+        prob.adjoint_shot(0, D, W)
+        tc = time.perf_counter() - t
+        out["cpu_baseline"] = {
+            "value": round(2 * nf * nz * nx / tc / 1e9, 5),
+            "unit": "Gpt-steps/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"shot 0, {nf} of {nw} frequencies: one Born and one "
+                      f"adjoint application (source march untimed), FP64 "
+                      f"numpy (FFTs and elementwise work on one thread), "
+                      f"{tc:.1f}s",
+        }
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -594,6 +860,8 @@ def main():
         return bench_autograd(args, P, synth, torch)
     if args.workload == "stream":
         return bench_stream(args, P, synth, torch)
+    if args.workload == "ssf":
+        return bench_ssf(args, P, synth, torch)
     w = synth.faulted2d_512x1024()
     Q, S = w.Q, w.S
     nshots = len(w.shots)

@@ -18,8 +18,11 @@
  *     kz = sqrt(w^2 s0_j^2 - kx^2) (e^{-|kz| dz} where evanescent), inverse
  *     FFT, times e^{-i w theta_j(x)}, times a lateral cosine taper of ntap
  *     cells per side (time runs as e^{+i w t}: every step adds traveltime);
- *   - source at column xs of level 0 with the spectrum of a Ricker wavelet
- *     (peak f0, delay 1.5/f0); S_{j+1} = E_j S_j; Born weights
+ *   - source at column xs of level 0: S_0 = F(w) (-i / (2 w s)) there, F
+ *     the spectrum of a Ricker wavelet (peak f0, delay 1.5/f0) and s the
+ *     slowness at the source (the one-way form of a 2-D point source: the
+ *     field below it is dx F times the outgoing Helmholtz Green's
+ *     function); S_{j+1} = E_j S_j; Born weights
  *     W_j = -i (w dz/2) s_j S_j (first-order change of the split-step phase
  *     for a relative squared-slowness perturbation m);
  *   - A (de-migration, eq. 1): R_{nz-1} = W_{nz-1} m_{nz-1},

@@ -27,8 +27,14 @@ level, then a split-step phase in space for the lateral variation):
   exp(-i w theta_j(x)), times a lateral taper tau(x) (cosine over ntap
   cells at each side, 1 inside). Time runs as exp(+i w t), so each step
   adds traveltime. E_j^H undoes the factors in reverse with conjugates.
-* Source at column xs of level 0: S_0 = F(w) delta(x - xs), F the DFT of the
-  Ricker wavelet of peak f0 delayed by 1.5/f0; S_{j+1} = E_j S_j.
+* Source at column xs of level 0:
+  S_0 = F(w) (-i / (2 w s(0, xs))) delta(x - xs), F the DFT of the Ricker
+  wavelet of peak f0 delayed by 1.5/f0; S_{j+1} = E_j S_j. The factor
+  -i/(2 w s) is the vertical-incidence one-way form of a 2-D point source:
+  with it the field below the source is dx F G, G = (-i/4) H0^(2)(w s r)
+  the outgoing Green's function of the Helmholtz equation, so the one-way
+  source radiates like the two-way point source of the finite-difference
+  operator.
 * Born scattering at level j of a relative squared-slowness perturbation m
   (the same m as the finite-difference operator): the first-order change of
   the split-step phase when s becomes s (1 + m/2), injected as
@@ -160,7 +166,8 @@ class SsfProblem:
         sh = self.shots[i]
         nz, nx = self.grid.model_shape
         S = np.zeros((self.nw, nx), dtype=np.complex128)
-        S[:, sh.xs] = self.wavelet(sh.f0)
+        S[:, sh.xs] = self.wavelet(sh.f0) * (
+            -0.5j / (self.omegas * self.s[0, sh.xs]))
         W = np.empty((nz, self.nw, nx), dtype=np.complex128)
         for j in range(nz):
             W[j] = -0.5j * self.dz * self.omegas[:, None] * self.s[j] * S

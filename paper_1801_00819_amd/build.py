@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "libbrrlsm.so")
 SOURCES = ["stencil2d.hip", "march2d.hip", "march2t.hip", "stencil3d.hip",
            "blas.hip", "engine.hip", "ssf.hip", "ssf_engine.hip"]
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed fp32 instructions (v_pk_*_f32) in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -39,7 +39,7 @@ def build(verbose: bool = False) -> str:
                   for s, o in zip(srcs, objs)]:
             f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + ["-o", tmp] + objs
+    cmd = [hipcc] + FLAGS + ["-shared", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

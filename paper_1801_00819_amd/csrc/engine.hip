@@ -60,6 +60,7 @@ struct Slot {
   float* segd2 = nullptr;    // [ckpt_k][nz][nx] (checkpoint mode)
   float* wav = nullptr;      // [nt_max]
   float* illum = nullptr;    // [nz][nx] sum of squared Born sources (cache)
+  bool illum_ready = false;  // illum holds this shot's sum
   int* rptr = nullptr;       // [ntiles_max + 1]
   int2* rent = nullptr;      // [nrec_max]
   int* rsidx = nullptr;      // [nrec_max]
@@ -463,16 +464,11 @@ int ensure_backgrounds(brls_ctx* c) {
                      0, wr, 1, n & 1)))
         return rc;
   }
-  // cache mode: each new shot's illumination (sum of its squared stored
-  // Born-source frames), for the preconditioner
-  if (!c->ckpt_k)
-    for (int i : todo) {
-      const Slot& sl = c->slots[i];
-      HIPCHECK(c, launch_sumsq_frames(sl.d2, std::max(sl.nt - 1, 0),
-                                      c->mplane, sl.illum, c->st));
-    }
   HIPCHECK(c, hipStreamSynchronize(c->st));
-  for (int i : todo) c->slots[i].bg_ready = true;
+  for (int i : todo) {
+    c->slots[i].bg_ready = true;
+    c->slots[i].illum_ready = false;
+  }
   return BRLS_OK;
 }
 
@@ -481,10 +477,19 @@ constexpr double kIllumEps = 0.01;
 
 int read_scalars(brls_ctx* c, double* out, int n);
 
-// Window illumination (sum over the window's slots) into out.
+// Window illumination (sum over the window's slots) into out. Each shot's
+// own sum of its squared stored Born-source frames is formed the first
+// time a window holding it needs it (cache mode only).
 int window_illumination(brls_ctx* c, float* out) {
   int rc;
   if ((rc = ensure_tab(c)) || (rc = ensure_backgrounds(c))) return rc;
+  for (int i : c->order) {
+    Slot& sl = c->slots[i];
+    if (sl.illum_ready) continue;
+    HIPCHECK(c, launch_sumsq_frames(sl.d2, std::max(sl.nt - 1, 0), c->mplane,
+                                    sl.illum, c->st));
+    sl.illum_ready = true;
+  }
   HIPCHECK(c, launch_fill_f32(out, c->mplane, 0.f, c->st));
   for (int i : c->order)
     HIPCHECK(c, launch_axpy(out, c->slots[i].illum, 1.0, c->mplane, c->st));

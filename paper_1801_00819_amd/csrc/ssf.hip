@@ -10,14 +10,21 @@
 // radix-2 pass first when log2 N is odd) whose first input and last output
 // are already in the register layout, so an N-point FFT needs
 // ceil(log2 N / 2) - 1 exchanges through LDS, one barrier each (two LDS
-// buffers used alternately). Twiddles depend only on the thread and the
-// pass, so they sit in registers for the whole march.
+// buffers used alternately, addresses swizzled against bank conflicts).
+// Twiddles depend only on the thread and the pass, so they sit in
+// registers for the whole march.
 //
-// Phase angles (kz dz and w theta) are formed and reduced in double and
-// only then rounded to float for sincos: the same rounded factor is applied
-// at every level, so a float error in the angle would grow linearly with
-// depth.
+// The phase factors depend on the frequency, the level and the column but
+// not on the shot: they are tabulated once per context (k_ssf_tables) and
+// the operator marches read them, with the Born weights, one level ahead
+// of their use. Their angles (kz dz and w theta) are formed and reduced in
+// double and only then rounded to float: the same rounded factor is
+// applied at every level, so a float error in the angle would grow
+// linearly with depth. The source march, which runs once per shot and
+// whose Born weights every later application reuses, runs in double.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "ssf_kernels.h"
 
@@ -94,6 +101,23 @@ __device__ inline double2 cis<double>(double a) {
   return make_double2(c, s);
 }
 
+// Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8),
+// and each XCD has its own L2. Block b serves frequency
+// k = (b mod 8) + 8 ((b / 8) / nshots) and shot (b / 8) mod nshots, so the
+// shots of one frequency run back to back on one XCD and share that
+// frequency's phase-table rows in its L2. Blocks past the last frequency
+// exit at once. Returns false for those.
+__device__ inline bool item_of(int b, int nshots, int nw, int* i, int* k) {
+  const int idx = b >> 3;
+  const int kk = idx / nshots;
+  *i = idx - kk * nshots;
+  *k = (b & 7) + 8 * kk;
+  return *k < nw;
+}
+__host__ inline int item_blocks(int nshots, int nw) {
+  return 8 * ((nw + 7) / 8) * nshots;
+}
+
 template <int L>
 struct Geo {
   static constexpr int N = 1 << L;
@@ -125,6 +149,13 @@ __device__ void load_twiddles(Twiddles<L, V>& T, const V* __restrict__ tw,
   }
 }
 
+// LDS slot of FFT element p: the low four bits (sixteen complex numbers,
+// 128 bytes) XORed with 5 * ((p >> 4) & 3). The Stockham passes write
+// elements 4 apart (first pass) and groups of 4 elements 16 apart (second
+// pass); with the swizzle every 16 consecutive lanes of those writes, and
+// of the contiguous reads, touch 16 different 8-byte bank pairs.
+__device__ inline int sw(int p) { return p ^ (((p >> 4) & 3) * 5); }
+
 // Forward DFT (e^{-2 pi i q x / N}) of the N points held four per thread,
 // in place in the same layout (frequency q = t + r N/4 afterwards).
 template <int L, typename V>
@@ -135,15 +166,15 @@ __device__ void fft(V v[4], V* __restrict__ b0, V* __restrict__ b1,
   if constexpr (Geo<L>::kOdd) {
     V* y = pb ? b1 : b0;
     if (on) {
-      y[2 * t] = cadd(v[0], v[2]);
-      y[2 * t + 1] = csub(v[0], v[2]);
-      y[2 * t + 2 * Q] = cadd(v[1], v[3]);
-      y[2 * t + 2 * Q + 1] = csub(v[1], v[3]);
+      y[sw(2 * t)] = cadd(v[0], v[2]);
+      y[sw(2 * t + 1)] = csub(v[0], v[2]);
+      y[sw(2 * t + 2 * Q)] = cadd(v[1], v[3]);
+      y[sw(2 * t + 2 * Q + 1)] = csub(v[1], v[3]);
     }
     __syncthreads();
     if (on) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = y[t + r * Q];
+      for (int r = 0; r < 4; ++r) v[r] = y[sw(t + r * Q)];
     }
     pb ^= 1;
   }
@@ -170,12 +201,12 @@ __device__ void fft(V v[4], V* __restrict__ b0, V* __restrict__ b1,
     const int base = (t - jm) * 4 + jm;
     if (on) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) y[base + r * Ns] = v[r];
+      for (int r = 0; r < 4; ++r) y[sw(base + r * Ns)] = v[r];
     }
     __syncthreads();
     if (on) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = y[t + r * Q];
+      for (int r = 0; r < 4; ++r) v[r] = y[sw(t + r * Q)];
     }
     pb ^= 1;
   }
@@ -206,12 +237,17 @@ __device__ inline typename Cplx<T>::V kz_phase(double ws0, double kx2,
 }
 
 // State of one workgroup's march: its frequency and the thread's columns.
+// Threads beyond N/4 (only when N < 256) shadow column tx = t mod N/4 for
+// their loads, so every load is in bounds without a branch; they store
+// nothing.
 template <int L, typename T>
 struct March {
   using V = typename Cplx<T>::V;
-  int t;
+  int t, tx;
+  bool on;
   double w;        // angular frequency
   double kx2[4];   // squared wavenumbers of the thread's four q
+  T tau[4];        // taper at the thread's four columns
   Twiddles<L, V> tw;
   int pb = 0;
 };
@@ -221,6 +257,8 @@ __device__ void march_init(March<L, T>& s, const SsfArgs& a, int k,
                            const typename Cplx<T>::V* tw) {
   constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
   s.t = threadIdx.x;
+  s.tx = s.t & (Q - 1);
+  s.on = s.t < Q;
   s.w = (double)(a.k0 + k) * a.dw;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -228,55 +266,92 @@ __device__ void march_init(March<L, T>& s, const SsfArgs& a, int k,
     const int qs = r < 2 ? q : q - N;
     const double kx = qs * a.kx_unit;
     s.kx2[r] = kx * kx;
+    s.tau[r] = (T)a.tau[s.tx + r * Q];
   }
   load_twiddles<L>(s.tw, tw, s.t);
 }
 
-// v <- E_j v
-template <int L, typename T, typename V>
-__device__ void step_down(March<L, T>& s, const SsfArgs& a, int j, V v[4],
-                          V* b0, V* b1) {
+// The medium at one level, loaded ahead of the FFTs that precede its use.
+struct Level {
+  double s0;     // reference slowness
+  double th[4];  // split-step times at the thread's columns
+};
+
+template <int L>
+__device__ inline void load_level(Level& lv, const SsfArgs& a, int j,
+                                  int tx) {
   constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
+  lv.s0 = a.s0[j];
+  const double* th = a.theta + (int64_t)j * N;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) lv.th[r] = th[tx + r * Q];
+}
+
+// One level's precomputed phase factors at the thread's four q and x.
+struct Phases {
+  float2 p[4];   // wavenumber-domain factor / N
+  float2 ss[4];  // split-step factor times the taper
+};
+
+template <int L>
+__device__ inline void load_phases(Phases& ph, const SsfArgs& a, int k,
+                                   int j, int tx) {
+  constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
+  const int64_t row = ((int64_t)k * a.nz + j) * N;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    ph.p[r] = a.ptab[row + tx + r * Q];
+    ph.ss[r] = a.sstab[row + tx + r * Q];
+  }
+}
+
+// v <- E_j v from the level's phase factors (float marches)
+template <int L>
+__device__ void step_down_tab(March<L, float>& s, const Phases& ph,
+                              float2 v[4], float2* b0, float2* b1) {
+  fft<L, float2>(v, b0, b1, s.tw, s.t, s.pb);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = cmul(v[r], ph.p[r]);
+  ifft<L, float2>(v, b0, b1, s.tw, s.t, s.pb);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = cmul(v[r], ph.ss[r]);
+}
+
+// v <- E_j^H v from the level's phase factors
+template <int L>
+__device__ void step_up_adj_tab(March<L, float>& s, const Phases& ph,
+                                float2 v[4], float2* b0, float2* b1) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float2 c = ph.ss[r];
+    c.y = -c.y;
+    v[r] = cmul(v[r], c);
+  }
+  fft<L, float2>(v, b0, b1, s.tw, s.t, s.pb);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float2 c = ph.p[r];
+    c.y = -c.y;
+    v[r] = cmul(v[r], c);
+  }
+  ifft<L, float2>(v, b0, b1, s.tw, s.t, s.pb);
+}
+
+// v <- E_j v, with lv the medium of level j
+template <int L, typename T, typename V>
+__device__ void step_down(March<L, T>& s, const SsfArgs& a, const Level& lv,
+                          V v[4], V* b0, V* b1) {
+  constexpr int N = Geo<L>::N;
   constexpr T kInvN = T(1) / N;
   fft<L, V>(v, b0, b1, s.tw, s.t, s.pb);
-  const double ws0 = s.w * a.s0[j];
+  const double ws0 = s.w * lv.s0;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     v[r] = cscale(cmul(v[r], kz_phase<T>(ws0, s.kx2[r], a.dz)), kInvN);
   ifft<L, V>(v, b0, b1, s.tw, s.t, s.pb);
-  if (s.t < Q) {
-    const double* th = a.theta + (int64_t)j * N;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int x = s.t + r * Q;
-      v[r] = cscale(cmul(v[r], cis<T>(-s.w * th[x])), (T)a.tau[x]);
-    }
-  }
-}
-
-// v <- E_j^H v
-template <int L, typename T, typename V>
-__device__ void step_up_adj(March<L, T>& s, const SsfArgs& a, int j, V v[4],
-                            V* b0, V* b1) {
-  constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
-  constexpr T kInvN = T(1) / N;
-  if (s.t < Q) {
-    const double* th = a.theta + (int64_t)j * N;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int x = s.t + r * Q;
-      v[r] = cscale(cmul(v[r], cis<T>(s.w * th[x])), (T)a.tau[x]);
-    }
-  }
-  fft<L, V>(v, b0, b1, s.tw, s.t, s.pb);
-  const double ws0 = s.w * a.s0[j];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    V p = kz_phase<T>(ws0, s.kx2[r], a.dz);
-    p.y = -p.y;
-    v[r] = cscale(cmul(v[r], p), kInvN);
-  }
-  ifft<L, V>(v, b0, b1, s.tw, s.t, s.pb);
+  for (int r = 0; r < 4; ++r)
+    v[r] = cscale(cmul(v[r], cis<T>(-s.w * lv.th[r])), s.tau[r]);
 }
 
 // --- source: Born weights W_j = -i (w dz/2) s_j S_j for one slot ---------
@@ -290,27 +365,31 @@ __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_source(
   const int k = blockIdx.x;
   March<L, double> s;
   march_init<L, double>(s, a, k, a.tw64);
-  const bool on = s.t < Q;
   double2 v[4];
   const double2 f = a.wav[(int64_t)slot * a.nw + k];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
-    v[r] = (on && s.t + r * Q == xs) ? f : czero<double2>();
+    v[r] = (s.on && s.t + r * Q == xs) ? f : czero<double2>();
   float2* Wb = a.W + ((int64_t)slot * a.nw + k) * a.nz * N;
   const double c = 0.5 * s.w * a.dz;
+  Level cur;
+  load_level<L>(cur, a, 0, s.tx);
   for (int j = 0; j < a.nz; ++j) {
-    if (on) {
-      const double* th = a.theta + (int64_t)j * N;
-      const double s0 = a.s0[j];
+    if (s.on) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int x = s.t + r * Q;
-        const double cs = c * (s0 + th[x] / a.dz);  // (w dz / 2) s_j(x)
+        const double cs = c * (cur.s0 + cur.th[r] / a.dz);  // (w dz/2) s_j
         Wb[(int64_t)j * N + x] =
             make_float2((float)(cs * v[r].y), (float)(-cs * v[r].x));
       }
     }
-    if (j + 1 < a.nz) step_down<L, double>(s, a, j, v, b0, b1);
+    if (j + 1 < a.nz) {
+      Level nxt;
+      load_level<L>(nxt, a, j + 1, s.tx);
+      step_down<L, double>(s, a, cur, v, b0, b1);
+      cur = nxt;
+    }
   }
 }
 
@@ -320,39 +399,43 @@ __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_born(
     SsfArgs a, const float* __restrict__ m, float* __restrict__ d) {
   constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
   __shared__ float2 b0[N], b1[N];
-  const int item = blockIdx.x;
-  const int i = item / a.nw, k = item - i * a.nw;
+  int i, k;
+  if (!item_of(blockIdx.x, a.nshots, a.nw, &i, &k)) return;
   const SsfShotDev sh = a.tab[i];
   March<L, float> s;
   march_init<L, float>(s, a, k, a.tw);
-  const bool on = s.t < Q;
   const float2* Wb = a.W + ((int64_t)sh.slot * a.nw + k) * a.nz * N;
   float2 v[4];
   {
     const int j = a.nz - 1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int x = s.t + r * Q;
-      v[r] = on ? cscale(Wb[(int64_t)j * N + x], m[(int64_t)j * N + x])
-                : czero<float2>();
+      const int x = s.tx + r * Q;
+      v[r] = cscale(Wb[(int64_t)j * N + x], m[(int64_t)j * N + x]);
     }
   }
   for (int j = a.nz - 2; j >= 0; --j) {
-    step_down<L, float>(s, a, j, v, b0, b1);
-    if (on) {
+    // this level's operands, in flight while the FFTs run
+    Phases ph;
+    load_phases<L>(ph, a, k, j, s.tx);
+    float2 wv[4];
+    float mv[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int x = s.t + r * Q;
-        const float2 wv = Wb[(int64_t)j * N + x];
-        const float mv = m[(int64_t)j * N + x];
-        v[r].x = fmaf(wv.x, mv, v[r].x);
-        v[r].y = fmaf(wv.y, mv, v[r].y);
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int x = s.tx + r * Q;
+      wv[r] = Wb[(int64_t)j * N + x];
+      mv[r] = m[(int64_t)j * N + x];
+    }
+    step_down_tab<L>(s, ph, v, b0, b1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      v[r].x = fmaf(wv[r].x, mv[r], v[r].x);
+      v[r].y = fmaf(wv[r].y, mv[r], v[r].y);
     }
   }
   // gather the receivers' columns of R_0
   __syncthreads();
-  if (on) {
+  if (s.on) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) b0[s.t + r * Q] = v[r];
   }
@@ -372,12 +455,12 @@ __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_adjoint(
     SsfArgs a, const float* __restrict__ d, float* __restrict__ part) {
   constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
   __shared__ float2 b0[N], b1[N];
-  const int item = blockIdx.x;
-  const int i = item / a.nw, k = item - i * a.nw;
+  int i, k;
+  if (!item_of(blockIdx.x, a.nshots, a.nw, &i, &k)) return;
+  const int item = i * a.nw + k;  // this pair's image slice (adjoint)
   const SsfShotDev sh = a.tab[i];
   March<L, float> s;
   march_init<L, float>(s, a, k, a.tw);
-  const bool on = s.t < Q;
   const float2* Wb = a.W + ((int64_t)sh.slot * a.nw + k) * a.nz * N;
   // the receivers' data placed in their columns (repeats summed in order)
   float2 v[4];
@@ -388,7 +471,7 @@ __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_adjoint(
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       float2 acc = make_float2(0.f, 0.f);
-      if (on) {
+      if (s.on) {
         const int x = s.t + r * Q;
         for (int e = cp[x]; e < cp[x + 1]; ++e) {
           const int ri = ci[e];
@@ -400,25 +483,93 @@ __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_adjoint(
     }
   }
   float* pb = part + (int64_t)item * a.nz * N;
-  for (int j = 0; j < a.nz; ++j) {
-    if (on) {
+  // level j's phases and weights are loaded one level ahead
+  Phases cur;
+  load_phases<L>(cur, a, k, 0, s.tx);
+  float2 wcur[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int x = s.t + r * Q;
-        const float2 wv = Wb[(int64_t)j * N + x];
-        pb[(int64_t)j * N + x] = fmaf(wv.x, v[r].x, wv.y * v[r].y);
-      }
+  for (int r = 0; r < 4; ++r) wcur[r] = Wb[s.tx + r * Q];
+  for (int j = 0; j < a.nz; ++j) {
+    if (s.on) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        pb[(int64_t)j * N + s.t + r * Q] =
+            fmaf(wcur[r].x, v[r].x, wcur[r].y * v[r].y);
     }
-    if (j + 1 < a.nz) step_up_adj<L, float>(s, a, j, v, b0, b1);
+    if (j + 1 < a.nz) {
+      Phases nxt;
+      load_phases<L>(nxt, a, k, j + 1, s.tx);
+      float2 wnxt[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        wnxt[r] = Wb[(int64_t)(j + 1) * N + s.tx + r * Q];
+      step_up_adj_tab<L>(s, cur, v, b0, b1);
+      cur = nxt;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) wcur[r] = wnxt[r];
+    }
   }
 }
 
-__global__ void k_ssf_image_sum(const float* __restrict__ part, int items,
-                                int64_t npts, float* __restrict__ img) {
+// Phase tables of every (frequency, level, column): the wavenumber-domain
+// factor divided by N, and the split-step factor times the taper, each
+// formed from its angle in double and rounded once to float.
+__global__ __launch_bounds__(256) void k_ssf_tables(SsfArgs a, int n,
+                                                    float2* ptab,
+                                                    float2* sstab) {
+  const int64_t total = (int64_t)a.nw * a.nz * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(e % n);
+    const int64_t kj = e / n;
+    const int j = (int)(kj % a.nz);
+    const int k = (int)(kj / a.nz);
+    const double w = (double)(a.k0 + k) * a.dw;
+    const int qs = q < n / 2 ? q : q - n;
+    const double kx = qs * a.kx_unit;
+    ptab[e] = cscale(kz_phase<float>(w * a.s0[j], kx * kx, a.dz),
+                     1.0f / n);
+    sstab[e] = cscale(cis<float>(-w * a.theta[(int64_t)j * n + q]),
+                      a.tau[q]);
+  }
+}
+
+// img = sum over items of part, in a fixed order: item groups of
+// consecutive items summed into double partials (each thread four
+// consecutive points), then the groups in order.
+constexpr int kSumGroups = kSsfSumGroups;
+
+__global__ __launch_bounds__(256) void k_ssf_sum_groups(
+    const float* __restrict__ part, int items, int64_t npts,
+    double* __restrict__ psum) {
+  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int g = blockIdx.y;
+  if (p >= npts) return;
+  const int i0 = (int)((int64_t)items * g / kSumGroups);
+  const int i1 = (int)((int64_t)items * (g + 1) / kSumGroups);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const float4 v = *reinterpret_cast<const float4*>(part + (int64_t)i * npts
+                                                      + p);
+    a0 += v.x;
+    a1 += v.y;
+    a2 += v.z;
+    a3 += v.w;
+  }
+  double* o = psum + (int64_t)g * npts + p;
+  o[0] = a0;
+  o[1] = a1;
+  o[2] = a2;
+  o[3] = a3;
+}
+
+__global__ __launch_bounds__(256) void k_ssf_sum_final(
+    const double* __restrict__ psum, int64_t npts, float* __restrict__ img) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npts) return;
   double acc = 0.0;
-  for (int i = 0; i < items; ++i) acc += part[(int64_t)i * npts + p];
+#pragma unroll
+  for (int g = 0; g < kSumGroups; ++g) acc += psum[(int64_t)g * npts + p];
   img[p] = (float)acc;
 }
 
@@ -478,7 +629,8 @@ hipError_t launch_ssf_born(const SsfArgs& a, const float* m, float* d,
   const int items = a.nshots * a.nw;
   if (items <= 0) return hipSuccess;
   SSF_DISPATCH(a.log2n,
-               hipLaunchKernelGGL(k_ssf_born<L>, dim3(items),
+               hipLaunchKernelGGL(k_ssf_born<L>,
+                                  dim3(item_blocks(a.nshots, a.nw)),
                                   dim3(Geo<L>::kBlock), 0, st, a, m, d));
   return hipGetLastError();
 }
@@ -488,17 +640,33 @@ hipError_t launch_ssf_adjoint(const SsfArgs& a, const float* d, float* part,
   const int items = a.nshots * a.nw;
   if (items <= 0) return hipSuccess;
   SSF_DISPATCH(a.log2n,
-               hipLaunchKernelGGL(k_ssf_adjoint<L>, dim3(items),
+               hipLaunchKernelGGL(k_ssf_adjoint<L>,
+                                  dim3(item_blocks(a.nshots, a.nw)),
                                   dim3(Geo<L>::kBlock), 0, st, a, d, part));
   return hipGetLastError();
 }
 
+hipError_t launch_ssf_tables(const SsfArgs& a, float2* ptab, float2* sstab,
+                             hipStream_t st) {
+  const int n = 1 << a.log2n;
+  const int64_t total = (int64_t)a.nw * a.nz * n;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(k_ssf_tables, dim3((unsigned)blocks), dim3(256), 0, st,
+                     a, n, ptab, sstab);
+  return hipGetLastError();
+}
+
 hipError_t launch_ssf_image_sum(const float* part, int items, int64_t npts,
-                                float* img, hipStream_t st) {
+                                float* img, double* psum, hipStream_t st) {
   if (npts <= 0) return hipSuccess;
+  if (npts % 4) return hipErrorInvalidValue;
   const int blk = 256;
-  hipLaunchKernelGGL(k_ssf_image_sum, dim3((npts + blk - 1) / blk), dim3(blk),
-                     0, st, part, items, npts, img);
+  hipLaunchKernelGGL(k_ssf_sum_groups,
+                     dim3((npts / 4 + blk - 1) / blk, kSumGroups), dim3(blk),
+                     0, st, part, items, npts, psum);
+  hipLaunchKernelGGL(k_ssf_sum_final, dim3((npts + blk - 1) / blk), dim3(blk),
+                     0, st, psum, npts, img);
   return hipGetLastError();
 }
 

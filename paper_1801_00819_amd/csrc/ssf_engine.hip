@@ -50,6 +50,7 @@ struct brls_ssf_ctx {
   int k0 = 0, nw = 0;
   double df = 0.0;
   int64_t M = 0;      // model points nz * nx
+  std::vector<double> slow0;  // slowness of the top level (sources)
   int64_t seg = 0;    // floats per slot of a data vector: 2 nw nrec_max
   SsfArgs args{};
   // medium tables
@@ -60,6 +61,7 @@ struct brls_ssf_ctx {
   // per slot
   float2* W = nullptr;
   double2* wav = nullptr;
+  float2 *ptab = nullptr, *sstab = nullptr;  // phase tables
   int *rec = nullptr, *colptr = nullptr, *cidx = nullptr;
   SsfShotDev* tab = nullptr;
   bool tab_dirty = true;
@@ -70,6 +72,7 @@ struct brls_ssf_ctx {
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr,
         *dtime = nullptr;
   double *partial = nullptr, *scal = nullptr;
+  double* psum = nullptr;  // image-sum partials
   int* flag = nullptr;
   std::vector<SsfSlot> slots;
   std::vector<int> order;
@@ -199,7 +202,7 @@ int adjoint_of(brls_ssf_ctx* c, const float* d_dev) {
   if ((rc = timed_end(c, &t))) return rc;
   if ((rc = timed_begin(c, kSSum, &t))) return rc;
   SCHECK(c, launch_ssf_image_sum(c->part, c->args.nshots * c->nw, c->M,
-                                 c->gbuf, c->st));
+                                 c->gbuf, c->psum, c->st));
   return timed_end(c, &t);
 }
 
@@ -321,6 +324,8 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
   std::vector<float> tau(N, 1.f);
   std::vector<float2> tw(N);
   std::vector<double2> tw64(N);
+  c->slow0.resize(N);
+  for (int x = 0; x < N; ++x) c->slow0[x] = 1.0 / (double)vel[x];
   for (int j = 0; j < nz; ++j) {
     double sum = 0.0;
     for (int x = 0; x < N; ++x) sum += 1.0 / (double)vel[(int64_t)j * N + x];
@@ -347,6 +352,8 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
       (rc = salloc(c, &c->tau, N)) || (rc = salloc(c, &c->tw, N)) ||
       (rc = salloc(c, &c->tw64, N)) ||
       (rc = salloc(c, &c->W, items * M)) ||
+      (rc = salloc(c, &c->ptab, (int64_t)c->nw * M)) ||
+      (rc = salloc(c, &c->sstab, (int64_t)c->nw * M)) ||
       (rc = salloc(c, &c->wav, items)) ||
       (rc = salloc(c, &c->rec, (int64_t)g.q_max * g.nrec_max)) ||
       (rc = salloc(c, &c->colptr, (int64_t)g.q_max * (N + 1))) ||
@@ -359,7 +366,8 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
       (rc = salloc(c, &c->q, D)) || (rc = salloc(c, &c->dscr, D)) ||
       (rc = salloc(c, &c->dtime, (int64_t)g.nt * g.nrec_max)) ||
       (rc = salloc(c, &c->partial, kDotBlocks)) ||
-      (rc = salloc(c, &c->scal, 4)) || (rc = salloc(c, &c->flag, 1)))
+      (rc = salloc(c, &c->scal, 4)) || (rc = salloc(c, &c->flag, 1)) ||
+      (rc = salloc(c, &c->psum, kSsfSumGroups * M)))
     return bail(rc);
   auto up = [&](void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st);
@@ -398,6 +406,11 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
   a.cidx = c->cidx;
   a.tab = c->tab;
   a.nshots = 0;
+  a.ptab = c->ptab;
+  a.sstab = c->sstab;
+  if (launch_ssf_tables(a, c->ptab, c->sstab, c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess)
+    return bail(sfail(c, BRLS_EDEVICE, "building the phase tables failed"));
   *out = c;
   return BRLS_OK;
 }
@@ -457,7 +470,10 @@ int brls_ssf_update(brls_ssf_ctx* c, const brls_ssf_shot* sh) {
     std::vector<int> fill(colptr.begin(), colptr.end() - 1);
     for (int i = 0; i < sh->nrec; ++i) cidx[fill[rec[i]]++] = i;
   }
-  // source spectrum: DFT of the sampled Ricker over the band
+  // source spectrum: the DFT of the sampled Ricker over the band (the
+  // kernel e^{-i w n dt} advanced by rotation, exact every 64 samples),
+  // times -i / (2 w s) at the source: the one-way form of a 2-D point
+  // source
   std::vector<double2> wav(c->nw);
   const int nt = c->g.nt;
   const double dt = c->g.dt;
@@ -465,13 +481,22 @@ int brls_ssf_update(brls_ssf_ctx* c, const brls_ssf_shot* sh) {
   for (int n = 0; n < nt; ++n) f[n] = ricker(n * dt, sh->f0);
   for (int k = 0; k < c->nw; ++k) {
     const double w = 2.0 * M_PI * (c->k0 + k) * c->df;
+    const double rc = std::cos(w * dt), rs = -std::sin(w * dt);
     double re = 0.0, im = 0.0;
-    for (int n = 0; n < nt; ++n) {
-      const double a = w * n * dt;
-      re += f[n] * std::cos(a);
-      im -= f[n] * std::sin(a);
+    for (int n0 = 0; n0 < nt; n0 += 64) {
+      double ec = std::cos(w * dt * n0), es = -std::sin(w * dt * n0);
+      const int n1 = std::min(nt, n0 + 64);
+      for (int n = n0; n < n1; ++n) {
+        re += f[n] * ec;
+        im += f[n] * es;
+        const double t = ec * rc - es * rs;
+        es = ec * rs + es * rc;
+        ec = t;
+      }
     }
-    wav[k] = make_double2(re * dt, im * dt);
+    // (re + i im) dt (-i / (2 w s)) = (im, -re) dt / (2 w s)
+    const double g = dt / (2.0 * w * c->slow0[sh->xs]);
+    wav[k] = make_double2(im * g, -re * g);
   }
   int rc;
   if ((rc = zero_slot(c, sidx))) return rc;

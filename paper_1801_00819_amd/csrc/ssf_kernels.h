@@ -30,6 +30,8 @@ struct SsfArgs {
   const double2* tw64;  // the same in double (source march)
   const double2* wav;   // [q_max][nw] source spectra
   float2* W;            // [q_max][nw][nz][nx] Born weights
+  const float2* ptab;   // [nw][nz][nx] wavenumber-domain phase / nx
+  const float2* sstab;  // [nw][nz][nx] split-step phase times taper
   const int* rec;       // [q_max][nrec_max] receiver columns
   const int* colptr;    // [q_max][nx + 1] receivers per column (CSR)
   const int* cidx;      // [q_max][nrec_max] receiver index per CSR entry
@@ -37,6 +39,9 @@ struct SsfArgs {
   int nshots;
 };
 
+// The phase tables of the medium (once per context).
+hipError_t launch_ssf_tables(const SsfArgs& a, float2* ptab, float2* sstab,
+                             hipStream_t st);
 // Born weights of one slot's shot for every frequency and level.
 hipError_t launch_ssf_source(const SsfArgs& a, int slot, int xs,
                              hipStream_t st);
@@ -46,9 +51,11 @@ hipError_t launch_ssf_born(const SsfArgs& a, const float* m, float* d,
 // Per-(shot, frequency) image contributions of A^T d, [items][nz][nx].
 hipError_t launch_ssf_adjoint(const SsfArgs& a, const float* d, float* part,
                               hipStream_t st);
-// img = sum over items of part, in item order.
+// img = sum over items of part in a fixed order (npts a multiple of 4;
+// psum: kSsfSumGroups * npts doubles of scratch).
+constexpr int kSsfSumGroups = 16;
 hipError_t launch_ssf_image_sum(const float* part, int items, int64_t npts,
-                                float* img, hipStream_t st);
+                                float* img, double* psum, hipStream_t st);
 // X[k][r] (re, im) = sum_n x[n][r] e^{-i w_k n dt} dt for one shot.
 hipError_t launch_ssf_data_dft(const float* x, int nt, int nrec, double dt,
                                int nw, int k0, double dw, float* X,
