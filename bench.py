@@ -59,11 +59,22 @@ TRAFFIC_2D = {
 }
 
 
-def kernel_sources_hash():
+# Counter-measured HBM bytes per launch of the split-step kernels on the
+# 5-shot window of the 256 x 1024 workload (rocprofv3 FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000, the factors a 512 MiB device copy reads in the same
+# program), valid for the kernel sources of that hash.
+TRAFFIC_SSF = {
+    "sources_sha256_16": "cf5ada9dabb0aa96",
+    "born": 2 * 1204829.1 * 1024 + 566.2 * 1024,
+    "adjoint": 2 * 1519524.4 * 1024 + 773120.0 * 1024,
+}
+
+
+def kernel_sources_hash(files=("stencil2d.hip", "march2d.hip", "march2t.hip",
+                               "march_common.h", "devutil.h", "layout.h")):
     import hashlib
     h = hashlib.sha256()
-    for f in ("stencil2d.hip", "march2d.hip", "march2t.hip",
-              "march_common.h", "devutil.h", "layout.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1801_00819_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
@@ -788,7 +799,9 @@ def bench_ssf(args, P, synth, torch):
             "peak": 157.3,
             "unit": "TFLOP/s",
             "frac": round(roof[dom]["tflops"] / 157.3, 4),
-            "traffic": None,
+            "traffic": (int(TRAFFIC_SSF[dom])
+                        if kernel_sources_hash(("ssf.hip", "ssf_kernels.h"))
+                        == TRAFFIC_SSF["sources_sha256_16"] else None),
             "avg_launch_us": round(roof[dom]["avg_us"], 1),
             "algorithmic_flops_per_launch": roof[dom]["flops"],
             "hbm": {"algorithmic_bytes_per_launch": roof[dom]["bytes"],

@@ -93,8 +93,10 @@ int brls_ssf_band(const brls_ssf_ctx* ctx, int32_t* k0, int32_t* nw,
                   double* df);
 
 /* Rank-one update (the paper's window update after eq. 10, Fig. 1): add a
- * shot to the window. Transforms its data to the band and builds its Born
- * weights W_j for every level and frequency (nw*nz*nx complex floats).
+ * shot to the window. Transforms its data to the band; its Born weights W_j
+ * for every level and frequency (nw*nz*nx complex floats) are built, with
+ * those of every other shot added since, at the next application of A or
+ * A^T (one launch for a whole slide).
  * Errors: BRLS_EFULL, BRLS_EDUP, BRLS_EINVAL (columns, sizes),
  * BRLS_ENONFINITE (data hold NaN/Inf). */
 int brls_ssf_update(brls_ssf_ctx* ctx, const brls_ssf_shot* shot);

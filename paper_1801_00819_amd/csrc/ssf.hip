@@ -357,12 +357,15 @@ __device__ void step_down(March<L, T>& s, const SsfArgs& a, const Level& lv,
 // --- source: Born weights W_j = -i (w dz/2) s_j S_j for one slot ---------
 // The source field is marched in double (it runs once per shot and every
 // later application of A and A^T reads its result); W is stored in float.
+// One block per (pending shot, frequency).
 template <int L>
 __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_source(
-    SsfArgs a, int slot, int xs) {
+    SsfArgs a, const SsfShotDev* __restrict__ pend) {
   constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
   __shared__ double2 b0[N], b1[N];
-  const int k = blockIdx.x;
+  const int pi = blockIdx.x / a.nw;
+  const int k = blockIdx.x - pi * a.nw;
+  const int slot = pend[pi].slot, xs = pend[pi].xs;
   March<L, double> s;
   march_init<L, double>(s, a, k, a.tw64);
   double2 v[4];
@@ -573,33 +576,53 @@ __global__ __launch_bounds__(256) void k_ssf_sum_final(
   img[p] = (float)acc;
 }
 
-// One thread per (frequency, receiver): the DFT sum in double, the kernel
-// e^{-i w n dt} advanced by rotation and reset exactly every 64 samples.
-__global__ void k_ssf_data_dft(const float* __restrict__ x, int nt, int nrec,
-                               double dt, int k0, double dw,
-                               float* __restrict__ X) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// X[k][r] = sum_n x[n][r] e^{-i w_k n dt} dt for one shot. A block serves
+// one frequency and 16 receivers; its 16 thread rows take 16 consecutive
+// chunks of the time axis. Each thread sums its chunk in double, the kernel
+// e^{-i w n dt} advanced by rotation from an exact start and reset exactly
+// every 64 samples; the chunks are then added in order.
+constexpr int kDftRecs = 16, kDftChunks = 16;
+
+__global__ __launch_bounds__(kDftRecs * kDftChunks) void k_ssf_data_dft(
+    const float* __restrict__ x, int nt, int nrec, double dt, int k0,
+    double dw, float* __restrict__ X) {
+  __shared__ double pre[kDftChunks][kDftRecs], pim[kDftChunks][kDftRecs];
+  const int rr = threadIdx.x % kDftRecs, c = threadIdx.x / kDftRecs;
+  const int r = blockIdx.x * kDftRecs + rr;
   const int k = blockIdx.y;
-  if (r >= nrec) return;
   const double w = (double)(k0 + k) * dw;
-  double rs, rc;
-  sincos(-w * dt, &rs, &rc);
+  const int len = (nt + kDftChunks - 1) / kDftChunks;
+  const int na = c * len, nb = min(nt, na + len);
   double re = 0.0, im = 0.0;
-  for (int n0 = 0; n0 < nt; n0 += 64) {
-    double es, ec;
-    sincos(-w * dt * n0, &es, &ec);
-    const int n1 = n0 + 64 < nt ? n0 + 64 : nt;
-    for (int n = n0; n < n1; ++n) {
-      const double xv = x[(int64_t)n * nrec + r];
-      re = fma(xv, ec, re);
-      im = fma(xv, es, im);
-      const double c2 = ec * rc - es * rs;
-      es = ec * rs + es * rc;
-      ec = c2;
+  if (r < nrec) {
+    double rs, rc;
+    sincos(-w * dt, &rs, &rc);
+    for (int n0 = na; n0 < nb; n0 += 64) {
+      double es, ec;
+      sincos(-w * dt * n0, &es, &ec);
+      const int n1 = min(nb, n0 + 64);
+      for (int n = n0; n < n1; ++n) {
+        const double xv = x[(int64_t)n * nrec + r];
+        re = fma(xv, ec, re);
+        im = fma(xv, es, im);
+        const double c2 = ec * rc - es * rs;
+        es = ec * rs + es * rc;
+        ec = c2;
+      }
     }
   }
-  X[((int64_t)k * nrec + r) * 2] = (float)(re * dt);
-  X[((int64_t)k * nrec + r) * 2 + 1] = (float)(im * dt);
+  pre[c][rr] = re;
+  pim[c][rr] = im;
+  __syncthreads();
+  if (c == 0 && r < nrec) {
+    double sre = 0.0, sim = 0.0;
+    for (int q = 0; q < kDftChunks; ++q) {
+      sre += pre[q][rr];
+      sim += pim[q][rr];
+    }
+    X[((int64_t)k * nrec + r) * 2] = (float)(sre * dt);
+    X[((int64_t)k * nrec + r) * 2 + 1] = (float)(sim * dt);
+  }
 }
 
 }  // namespace
@@ -615,12 +638,12 @@ __global__ void k_ssf_data_dft(const float* __restrict__ x, int nt, int nrec,
     default: return hipErrorInvalidValue;                       \
   }
 
-hipError_t launch_ssf_source(const SsfArgs& a, int slot, int xs,
-                             hipStream_t st) {
-  if (a.nw <= 0) return hipSuccess;
+hipError_t launch_ssf_source(const SsfArgs& a, const SsfShotDev* pend,
+                             int npend, hipStream_t st) {
+  if (a.nw <= 0 || npend <= 0) return hipSuccess;
   SSF_DISPATCH(a.log2n,
-               hipLaunchKernelGGL(k_ssf_source<L>, dim3(a.nw),
-                                  dim3(Geo<L>::kBlock), 0, st, a, slot, xs));
+               hipLaunchKernelGGL(k_ssf_source<L>, dim3(a.nw * npend),
+                                  dim3(Geo<L>::kBlock), 0, st, a, pend));
   return hipGetLastError();
 }
 
@@ -674,8 +697,9 @@ hipError_t launch_ssf_data_dft(const float* x, int nt, int nrec, double dt,
                                int nw, int k0, double dw, float* X,
                                hipStream_t st) {
   if (nw <= 0 || nrec <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ssf_data_dft, dim3((nrec + 63) / 64, nw), dim3(64), 0,
-                     st, x, nt, nrec, dt, k0, dw, X);
+  hipLaunchKernelGGL(k_ssf_data_dft, dim3((nrec + kDftRecs - 1) / kDftRecs, nw),
+                     dim3(kDftRecs * kDftChunks), 0, st, x, nt, nrec, dt, k0,
+                     dw, X);
   return hipGetLastError();
 }
 

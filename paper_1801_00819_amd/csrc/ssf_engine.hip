@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,7 @@ const char* kSsfTimerNames[kSNumKinds] = {"ssf_data_dft", "ssf_source",
 
 struct SsfSlot {
   bool used = false;
+  bool w_ready = false;  // Born weights built
   int64_t id = 0;
   int xs = 0, nrec = 0;
   double f0 = 0.0;
@@ -51,6 +53,8 @@ struct brls_ssf_ctx {
   double df = 0.0;
   int64_t M = 0;      // model points nz * nx
   std::vector<double> slow0;  // slowness of the top level (sources)
+  // band spectra of the Ricker wavelet, by peak frequency
+  std::map<double, std::vector<double2>> ricker_spectra;
   int64_t seg = 0;    // floats per slot of a data vector: 2 nw nrec_max
   SsfArgs args{};
   // medium tables
@@ -64,6 +68,7 @@ struct brls_ssf_ctx {
   float2 *ptab = nullptr, *sstab = nullptr;  // phase tables
   int *rec = nullptr, *colptr = nullptr, *cidx = nullptr;
   SsfShotDev* tab = nullptr;
+  SsfShotDev* pend = nullptr;  // shots whose Born weights are pending
   bool tab_dirty = true;
   // vectors
   float* part = nullptr;
@@ -164,7 +169,30 @@ int read_scalars(brls_ssf_ctx* c, double* out, int n) {
   return BRLS_OK;
 }
 
+// Born weights of every window shot added since the last application, in
+// one launch (a slide adds several shots; one launch keeps the chip full).
+int ensure_weights(brls_ssf_ctx* c) {
+  std::vector<SsfShotDev> h;
+  for (int sidx : c->order)
+    if (!c->slots[sidx].w_ready)
+      h.push_back(SsfShotDev{sidx, c->slots[sidx].xs, c->slots[sidx].nrec});
+  if (h.empty()) return BRLS_OK;
+  SCHECK(c, hipMemcpyAsync(c->pend, h.data(), h.size() * sizeof(SsfShotDev),
+                           hipMemcpyHostToDevice, c->st));
+  int rc;
+  SsfTimer t{};
+  if ((rc = timed_begin(c, kSSource, &t))) return rc;
+  SCHECK(c, launch_ssf_source(c->args, c->pend, (int)h.size(), c->st));
+  if ((rc = timed_end(c, &t))) return rc;
+  // the pending list must be on the device before the host vector goes
+  SCHECK(c, hipStreamSynchronize(c->st));
+  for (const auto& e : h) c->slots[e.slot].w_ready = true;
+  return BRLS_OK;
+}
+
 int ensure_tab(brls_ssf_ctx* c) {
+  int rc;
+  if ((rc = ensure_weights(c))) return rc;
   if (!c->tab_dirty) return BRLS_OK;
   std::vector<SsfShotDev> h;
   for (int sidx : c->order) {
@@ -359,6 +387,7 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
       (rc = salloc(c, &c->colptr, (int64_t)g.q_max * (N + 1))) ||
       (rc = salloc(c, &c->cidx, (int64_t)g.q_max * g.nrec_max)) ||
       (rc = salloc(c, &c->tab, g.q_max)) ||
+      (rc = salloc(c, &c->pend, g.q_max)) ||
       (rc = salloc(c, &c->part, items * M)) || (rc = salloc(c, &c->m, M)) ||
       (rc = salloc(c, &c->p, M)) || (rc = salloc(c, &c->s, M)) ||
       (rc = salloc(c, &c->gbuf, M)) || (rc = salloc(c, &c->min, M)) ||
@@ -471,32 +500,41 @@ int brls_ssf_update(brls_ssf_ctx* c, const brls_ssf_shot* sh) {
     for (int i = 0; i < sh->nrec; ++i) cidx[fill[rec[i]]++] = i;
   }
   // source spectrum: the DFT of the sampled Ricker over the band (the
-  // kernel e^{-i w n dt} advanced by rotation, exact every 64 samples),
-  // times -i / (2 w s) at the source: the one-way form of a 2-D point
-  // source
-  std::vector<double2> wav(c->nw);
+  // kernel e^{-i w n dt} advanced by rotation, exact every 64 samples; kept
+  // per peak frequency), times -i / (2 w s) at the source: the one-way form
+  // of a 2-D point source
   const int nt = c->g.nt;
   const double dt = c->g.dt;
-  std::vector<double> f(nt);
-  for (int n = 0; n < nt; ++n) f[n] = ricker(n * dt, sh->f0);
+  auto it = c->ricker_spectra.find(sh->f0);
+  if (it == c->ricker_spectra.end()) {
+    std::vector<double2> F(c->nw);
+    std::vector<double> f(nt);
+    for (int n = 0; n < nt; ++n) f[n] = ricker(n * dt, sh->f0);
+    for (int k = 0; k < c->nw; ++k) {
+      const double w = 2.0 * M_PI * (c->k0 + k) * c->df;
+      const double rc = std::cos(w * dt), rs = -std::sin(w * dt);
+      double re = 0.0, im = 0.0;
+      for (int n0 = 0; n0 < nt; n0 += 64) {
+        double ec = std::cos(w * dt * n0), es = -std::sin(w * dt * n0);
+        const int n1 = std::min(nt, n0 + 64);
+        for (int n = n0; n < n1; ++n) {
+          re += f[n] * ec;
+          im += f[n] * es;
+          const double t = ec * rc - es * rs;
+          es = ec * rs + es * rc;
+          ec = t;
+        }
+      }
+      F[k] = make_double2(re * dt, im * dt);
+    }
+    it = c->ricker_spectra.emplace(sh->f0, std::move(F)).first;
+  }
+  std::vector<double2> wav(c->nw);
   for (int k = 0; k < c->nw; ++k) {
     const double w = 2.0 * M_PI * (c->k0 + k) * c->df;
-    const double rc = std::cos(w * dt), rs = -std::sin(w * dt);
-    double re = 0.0, im = 0.0;
-    for (int n0 = 0; n0 < nt; n0 += 64) {
-      double ec = std::cos(w * dt * n0), es = -std::sin(w * dt * n0);
-      const int n1 = std::min(nt, n0 + 64);
-      for (int n = n0; n < n1; ++n) {
-        re += f[n] * ec;
-        im += f[n] * es;
-        const double t = ec * rc - es * rs;
-        es = ec * rs + es * rc;
-        ec = t;
-      }
-    }
-    // (re + i im) dt (-i / (2 w s)) = (im, -re) dt / (2 w s)
-    const double g = dt / (2.0 * w * c->slow0[sh->xs]);
-    wav[k] = make_double2(im * g, -re * g);
+    // (re + i im) (-i / (2 w s)) = (im, -re) / (2 w s)
+    const double g = 1.0 / (2.0 * w * c->slow0[sh->xs]);
+    wav[k] = make_double2(it->second[k].y * g, -it->second[k].x * g);
   }
   int rc;
   if ((rc = zero_slot(c, sidx))) return rc;
@@ -526,14 +564,11 @@ int brls_ssf_update(brls_ssf_ctx* c, const brls_ssf_shot* sh) {
                                   c->dobs + (int64_t)sidx * c->seg, c->st));
     if ((rc = timed_end(c, &t))) return rc;
   }
-  SsfTimer t{};
-  if ((rc = timed_begin(c, kSSource, &t))) return rc;
-  SCHECK(c, launch_ssf_source(c->args, sidx, sh->xs, c->st));
-  if ((rc = timed_end(c, &t))) return rc;
   // the host vectors above must outlive the asynchronous copies
   SCHECK(c, hipStreamSynchronize(c->st));
   SsfSlot& sl = c->slots[sidx];
   sl.used = true;
+  sl.w_ready = false;
   sl.id = sh->id;
   sl.xs = sh->xs;
   sl.nrec = sh->nrec;

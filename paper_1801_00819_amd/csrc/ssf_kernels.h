@@ -42,9 +42,10 @@ struct SsfArgs {
 // The phase tables of the medium (once per context).
 hipError_t launch_ssf_tables(const SsfArgs& a, float2* ptab, float2* sstab,
                              hipStream_t st);
-// Born weights of one slot's shot for every frequency and level.
-hipError_t launch_ssf_source(const SsfArgs& a, int slot, int xs,
-                             hipStream_t st);
+// Born weights of the listed shots (slot and source column of each) for
+// every frequency and level.
+hipError_t launch_ssf_source(const SsfArgs& a, const SsfShotDev* pend,
+                             int npend, hipStream_t st);
 // d (slot layout) = A m over the window's shots.
 hipError_t launch_ssf_born(const SsfArgs& a, const float* m, float* d,
                            hipStream_t st);
