@@ -126,6 +126,12 @@ def parse():
                          "window configuration")
     ap.add_argument("--ssf-windows", type=int, default=0,
                     help="ssf workload: windows of the chain to run (0: all)")
+    ap.add_argument("--ssf-data", default="nonlinear",
+                    choices=["nonlinear", "born"],
+                    help="ssf workload: finite-difference modelling in the "
+                         "true velocity minus that in the migration velocity "
+                         "(nonlinear), or two-way FD Born data of the "
+                         "reflectivity")
     ap.add_argument("--ops-only", action="store_true",
                     help="after setup run one 512 MiB device copy (the "
                          "counter calibration kernel) and one batched Born "
@@ -617,12 +623,15 @@ def bench_ssf(args, P, synth, torch):
     """Split-step Fourier shot-profile operator pair (the paper's own
     operator family) in the paper's window configuration on the 256 x 1024
     Marmousi stand-in: 240 shots, windows of 5 sliding by 3, 8 CG
-    iterations per window, warm-started. The observed data are two-way
-    finite-difference Born data of the same reflectivity (the library's
-    8th-order operator, sources and receivers 2 cells below the top of a
-    grid two rows taller), plus 1 % noise: the one-way operator never sees
-    its own modelling. Reports the chain's throughput, seconds per window,
-    per-kernel timing and the roofline of the dominant kernel."""
+    iterations per window, warm-started. The observed data come from the
+    library's two-way 8th-order finite-difference modelling on a grid two
+    rows taller (sources and receivers 2 cells down): by default the
+    modelling in the true (faulted, blocky) velocity minus that in the
+    migration velocity (nonlinear data, the paper's kind), or with
+    --ssf-data born the FD Born data of the reflectivity; plus 1 % noise.
+    The one-way operator never sees its own modelling. Reports the chain's
+    throughput, seconds per window, per-kernel timing and the roofline of
+    the dominant kernel."""
     from paper_1801_00819_amd.ssf import brls_ssf_open
     w = synth.ssf2d_256x1024()
     nz, nx, Q = w.nz, w.nx, w.Q
@@ -650,28 +659,73 @@ def bench_ssf(args, P, synth, torch):
     if args.ssf_windows > 0:
         windows = windows[:args.ssf_windows]
     need = sorted({i for win in windows for i in win})
-    # ---- two-way FD Born data (untimed) --------------------------------
+    # ---- FD data (untimed) ---------------------------------------------
     t0 = time.perf_counter()
-    vel_fd = np.concatenate([np.repeat(w.vel[:1], 2, 0), w.vel], 0)
-    m_fd = np.concatenate([np.zeros((2, nx)), w.m_true], 0)
-    fd = P.brls_open(2, nz + 2, 1, nx, 40, w.nt, nrec, 8, w.dx, w.dt, 0.0,
-                     vel_fd[:, None, :].astype(np.float32), device=True)
-    fd.set_tuning(*DEFAULT_TUNING)
-    m_fd_t = torch.from_numpy(m_fd[:, None, :].astype(np.float32)).cuda()
+
+    # the FD grid: two rows above the model (sources and receivers 2 cells
+    # down), and one row below at the larger of the two models' largest
+    # velocities, so that both modellings get the same sponge (its damping
+    # scales with the model's largest velocity) and the common wavefield,
+    # direct wave included, cancels in their difference
+    vcap = max(float(w.extra["vel_true"].max()), float(w.vel.max()))
+
+    def fd_grid(v):
+        return np.concatenate([np.repeat(v[:1], 2, 0), v,
+                               np.full((1, nx), vcap)], 0)[:, None, :] \
+            .astype(np.float32)
+    nzf = nz + 3
+    nonlinear = args.ssf_data == "nonlinear"
+    if nonlinear:
+        # modelling only: checkpointed backgrounds keep memory small
+        fds = [P.brls_open(2, nzf, 1, nx, 40, w.nt, nrec, 8, w.dx, w.dt,
+                           0.0, fd_grid(v), device=True, ckpt_interval=-1)
+               for v in (w.extra["vel_true"], w.vel)]
+        m_ref = w.extra["m_nonlinear"]
+    else:
+        fds = [P.brls_open(2, nzf, 1, nx, 40, w.nt, nrec, 8, w.dx, w.dt,
+                           0.0, fd_grid(w.vel), device=True)]
+        fds[0].set_tuning(*DEFAULT_TUNING)
+        m_fd = np.concatenate([np.zeros((2, nx)), w.m_true,
+                               np.zeros((1, nx))], 0)
+        m_fd_t = torch.from_numpy(m_fd[:, None, :].astype(np.float32)).cuda()
+        m_ref = w.m_true
     data = {}
     for b in range(0, len(need), 8):
         ids = need[b:b + 8]
-        for i in ids:
-            s = w.shots[i]
-            rec = np.stack([np.full(nrec, 2), np.zeros(nrec, int), s.rec],
-                           1).astype(np.int32)
-            fd.update(i, (2, 0, s.xs), rec, w.nt, s.f0, None)
-        d = fd.apply_born(m_fd_t).view(len(ids), w.nt, nrec)
-        for k, i in enumerate(fd.window()):
+        for fd in fds:
+            for i in ids:
+                s = w.shots[i]
+                rec = np.stack([np.full(nrec, 2), np.zeros(nrec, int),
+                                s.rec], 1).astype(np.int32)
+                fd.update(i, (2, 0, s.xs), rec, w.nt, s.f0, None)
+        if nonlinear:
+            d = fds[0].background_window() - fds[1].background_window()
+        else:
+            d = fds[0].apply_born(m_fd_t)
+        d = d.view(len(ids), w.nt, nrec)
+        if nonlinear:
+            # top mute: the true-minus-background difference also holds the
+            # head and diving waves of the blocky shallow section and the
+            # water-bottom reflection, which one-way continuation does not
+            # model; keep each trace from just below the water-bottom
+            # reflection time t0 + sqrt(x^2 + (2 z_w)^2) / v_w + 2 / f0
+            # (40 ms cosine ramp)
+            for k, i in enumerate(fds[0].window()):
+                s = w.shots[i]
+                off = torch.from_numpy(np.abs(s.rec - s.xs) * w.dx).cuda()
+                tm = 1.5 / s.f0 + torch.sqrt(off ** 2 + 400.0 ** 2) / 1500.0 \
+                    + 2.0 / s.f0
+                t = torch.arange(w.nt, device="cuda",
+                                 dtype=torch.float64)[:, None] * w.dt
+                ramp = torch.clamp((t - tm[None, :]) / 0.04, 0.0, 1.0)
+                d[k] *= (0.5 - 0.5 * torch.cos(np.pi * ramp)).float()
+        for k, i in enumerate(fds[0].window()):
             data[i] = d[k].clone()
-        for i in ids:
-            fd.downdate(i)
-    fd.close()
+        for fd in fds:
+            for i in ids:
+                fd.downdate(i)
+    for fd in fds:
+        fd.close()
     rms = float(np.sqrt(sum(float((x.double() ** 2).sum())
                             for x in data.values())
                         / sum(x.numel() for x in data.values())))
@@ -680,7 +734,7 @@ def bench_ssf(args, P, synth, torch):
     for i in need:
         data[i] += 0.01 * rms * torch.randn(data[i].shape, generator=gen,
                                             device="cuda")
-    log(f"ssf: FD Born data for {len(need)} shots in "
+    log(f"ssf: FD {args.ssf_data} data for {len(need)} shots in "
         f"{time.perf_counter() - t0:.1f}s")
 
     def open_ctx(lam):
@@ -758,10 +812,10 @@ def bench_ssf(args, P, synth, torch):
     # last window illuminates (from its leftmost receiver to its rightmost
     # source), the chain's image against that window's migration image
     lw = [w.shots[i] for i in windows[-1]]
-    zs = slice(16, nz - 16)
+    zs = slice(24, nz - 16)  # below the water bottom
     xs_ = slice(int(min(s.rec.min() for s in lw)),
                 int(max(s.xs for s in lw)) + 1)
-    mt = torch.from_numpy(w.m_true).cuda()
+    mt = torch.from_numpy(m_ref).cuda()
 
     def corr(a):
         a = a[zs, xs_].double()
@@ -785,8 +839,11 @@ def bench_ssf(args, P, synth, torch):
                                f"{len(windows)} windows of 5 shots sliding "
                                f"by 3 over {len(need)} shots, 96 receivers, "
                                f"{nw} frequencies {w.fmin}-{w.fmax} Hz, 8 CG "
-                               "iterations, two-way FD Born data + 1 % "
-                               "noise",
+                               "iterations, "
+                               + ("nonlinear FD data (true minus migration "
+                                  "velocity, top-muted)" if nonlinear else
+                                  "two-way FD Born data")
+                               + " + 1 % noise",
                    "model": [nz, nx]},
         "s_per_window": {"mean": round(float(np.mean(lat)), 4),
                          "p50": round(float(np.percentile(lat, 50)), 4),

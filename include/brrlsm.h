@@ -201,6 +201,16 @@ int brls_apply_born(brls_ctx* ctx, const float* m, float* d_out);
  * in window order). */
 int brls_apply_adjoint(brls_ctx* ctx, const float* d, float* m_out);
 
+/* Finite-difference modelling in the context's own velocity (the kind of
+ * data the paper's examples migrate: finite-difference shot gathers of a
+ * Ricker source, Examples section): every window shot's background
+ * wavefield u0 at its receivers, u0^n for n = 0 .. nt-1 (u0^0 = 0), in the
+ * window data layout. Nonlinear data of a model are the difference of this
+ * output for its true velocity and for a background velocity. Runs one
+ * background pass from rest; stored Born sources and checkpoints are left
+ * as they are. out: host or device per flags. */
+int brls_background_window(brls_ctx* ctx, float* out);
+
 /* Execution mode for the operator pair (BRLS_EXEC_*). Results agree across
  * modes to rounding of the image reduction order. */
 int brls_set_exec(brls_ctx* ctx, int32_t mode);

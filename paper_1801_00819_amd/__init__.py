@@ -212,6 +212,23 @@ class Context:
 
     apply_adjoint = brls_apply_adjoint
 
+    def brls_background_window(self, out=None):
+        """Finite-difference modelling in the context's velocity: each
+        window shot's background wavefield at its receivers, [nt][nrec] per
+        shot in window order."""
+        n = self.window_data_size()
+        if out is None:
+            if self.device:
+                import torch
+                out = torch.empty(n, dtype=torch.float32, device="cuda")
+            else:
+                out = np.empty(n, dtype=np.float32)
+        self._check(L.lib().brls_background_window(self._h,
+                                                   _ptr(out, self.device)))
+        return out
+
+    background_window = brls_background_window
+
     def brls_set_exec(self, mode: int):
         self._check(L.lib().brls_set_exec(self._h, int(mode)))
 

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "layout.h"
 
 namespace brls {
 
@@ -228,6 +229,28 @@ hipError_t launch_nonfinite(const float* x, int64_t n, int* flag,
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(n)), dim3(256), 0, st, x, n,
                      flag);
+  return hipGetLastError();
+}
+
+// dst[dat_off + (n + 1) nrec + r] = u^{n+1} at receiver r of every window
+// shot with n + 1 < nt: the background level n + 1 sits in field b[(n+1)&1]
+// (one-step kernels keep u of even and odd levels there; the two-step
+// kernels' field set s holds its u in f[s], and a background launch writes
+// set (n+1)&1).
+__global__ void k_gather_receivers(const ShotDev* tab, int n, float* dst) {
+  const ShotDev& s = tab[blockIdx.y];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n + 1 >= s.nt || r >= s.nrec) return;
+  dst[s.dat_off + (int64_t)(n + 1) * s.nrec + r] =
+      s.b[(n + 1) & 1][s.rsidx[r]];
+}
+
+hipError_t launch_gather_receivers(const ShotDev* tab, int nshots,
+                                   int nrec_max, int n, float* dst,
+                                   hipStream_t st) {
+  if (nshots <= 0 || nrec_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_receivers, dim3((nrec_max + 255) / 256, nshots),
+                     dim3(256), 0, st, tab, n, dst);
   return hipGetLastError();
 }
 

@@ -1222,6 +1222,44 @@ int brls_apply_born(brls_ctx* c, const float* m, float* d_out) {
   return BRLS_OK;
 }
 
+int brls_background_window(brls_ctx* c, float* out) {
+  if (!c || !out) return fail(c, BRLS_EINVAL, "NULL argument");
+  if (c->order.empty()) return BRLS_OK;
+  int rc;
+  if ((rc = ensure_tab(c))) return rc;
+  // one batched background pass over the window's shots from rest, no
+  // Born-source frames written (the stored ones stay valid); after each
+  // step the receivers' samples of the new level go to their segments
+  for (int i : c->order) {
+    Slot& sl = c->slots[i];
+    HIPCHECK(c, launch_fill_f32(c->ckpt_k ? sl.bgf : sl.fields,
+                                (c->ckpt_k ? 3 : fields_per_slot(c)) * c->fs,
+                                0.f, c->st));
+  }
+  HIPCHECK(c, launch_fill_f32(c->dscr, (int64_t)c->g.q_max * c->seg, 0.f,
+                              c->st));
+  const int nsh = (int)c->order.size();
+  const int ntm = nt_max_of(c, c->order);
+  for (int n = 0; n + 1 < ntm; ++n) {
+    if ((rc = step(c, kBackground, n, c->tab_dev, nsh,
+                   std::min(c->per_block, nsh), nullptr, nullptr, nullptr, 0,
+                   0, 1, n & 1)))
+      return rc;
+    HIPCHECK(c, launch_gather_receivers(c->tab_dev, nsh, c->g.nrec_max, n,
+                                        c->dscr, c->st));
+  }
+  int64_t off = 0;
+  for (int i : c->order) {
+    const Slot& sl = c->slots[i];
+    const int64_t nd = (int64_t)sl.nt * sl.nrec;
+    HIPCHECK(c, hipMemcpyAsync(out + off, c->dscr + sl.dat_off, nd * 4,
+                               out_kind(c), c->st));
+    off += nd;
+  }
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
 int brls_apply_adjoint(brls_ctx* c, const float* d, float* m_out) {
   if (!c || !d || !m_out) return fail(c, BRLS_EINVAL, "NULL argument");
   HIPCHECK(c, launch_fill_f32(c->dscr, (int64_t)c->g.q_max * c->seg, 0.f,

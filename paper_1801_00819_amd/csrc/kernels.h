@@ -91,6 +91,11 @@ hipError_t launch_recip_shift(float* y, const float* x, double shift,
 // partial sums, then out[0] = sum(x) (float64, fixed order)
 hipError_t launch_sum(const float* x, int64_t n, double* partial, double* out,
                       hipStream_t st);
+// Receiver samples of background level n + 1 of every window shot into
+// its segment of a data vector (see k_gather_receivers).
+hipError_t launch_gather_receivers(const ShotDev* tab, int nshots,
+                                   int nrec_max, int n, float* dst,
+                                   hipStream_t st);
 // flag[0] = 1 if any entry of x is NaN or Inf (flag must start at 0)
 hipError_t launch_nonfinite(const float* x, int64_t n, int* flag,
                             hipStream_t st);

@@ -442,9 +442,12 @@ def ssf_small(nz: int = 24, nx: int = 64, nt: int = 256, dt: float = 4e-3,
 def ssf2d_256x1024(nshots: int = 240) -> SsfWorkload:
     """Stand-in for the paper's Marmousi example (Examples section): 2-D,
     256 x 1024 at 12.5 m (3.2 x 12.8 km, 32-cell tapers at the sides), a
-    faulted layered velocity 1500 -> 4500 m/s smoothed over 9 cells as the
-    migration velocity, faulted layered reflectivity; 240 shots 25 m apart
-    (the paper's count and spacing), each with 96 receivers 25 m apart on an
+    200 m water layer over a faulted layered velocity 1500 -> 4500 m/s
+    (smoothed over 9 cells: the migration velocity), faulted layered
+    reflectivity (extra: the true velocity, and the high-passed squared-
+    slowness perturbation it carries against the migration velocity); 240
+    shots 25 m apart (the paper's count and spacing), each with 96
+    receivers 25 m apart on an
     off-end spread to the left of the source (near offset 100 m), 20 Hz
     Ricker, 4096 samples at 1 ms, band 3-40 Hz (151 frequencies); windows of
     5 shots sliding by 3, 8 CG iterations (the paper's configuration)."""
@@ -453,6 +456,7 @@ def ssf2d_256x1024(nshots: int = 240) -> SsfWorkload:
     z = np.arange(nz, dtype=np.float64)[:, None]
     vtrue = 1500.0 + 2600.0 * (z / (nz - 1)) ** 0.8 + 400.0 * b * (
         0.3 + 0.7 * z / (nz - 1))
+    vtrue[:16] = 1500.0  # water layer (200 m), as on top of Marmousi
     vel = _smooth2(vtrue, 4)
     m = faulted_reflectivity(nz, nx, rng(SEED_SSF2D_256, 0),
                              rng(SEED_SSF2D_256, 3))
@@ -461,6 +465,11 @@ def ssf2d_256x1024(nshots: int = 240) -> SsfWorkload:
         xs = 300 + 2 * i
         rec = np.array([xs - 8 - 2 * k for k in range(96)], dtype=np.int32)
         shots.append(SsfShot(i, xs, rec, 20.0))
+    # the perturbation nonlinear data of vtrue carry against the migration
+    # velocity: relative squared slowness, minus its 9-cell average
+    pert = (vel / vtrue) ** 2 - 1.0
     return SsfWorkload("ssf2d-256x1024", SEED_SSF2D_256, nz, nx, h, h, 4096,
                        1e-3, 3.0, 40.0, 32, vel, m, shots, Q=5, S=3, niter=8,
-                       lam_rel=1e-3, extra={"vel_true": vtrue})
+                       lam_rel=1e-3,
+                       extra={"vel_true": vtrue,
+                              "m_nonlinear": pert - _smooth2(pert, 4)})

@@ -538,3 +538,33 @@ def test_correction_regularised_chain_matches_oracle(P, mode):
     ctx.close()
     assert rel(img, ref.m) <= IMG_TOL
     assert rel(img, plain.m) > 10 * IMG_TOL
+
+
+@pytest.mark.parametrize("cfg", ["two-step", "staged", "marching", "ckpt"])
+@pytest.mark.parametrize("name", ["layers64", "ragged2d"])
+def test_background_window_matches_oracle(P, name, cfg):
+    """Finite-difference modelling in the context's velocity (the background
+    wavefield at every shot's receivers, u0^0 = 0 .. u0^{nt-1}) against the
+    oracle's, for each kernel form and with checkpointed backgrounds; A
+    applied afterwards is bitwise what it was before (the stored Born
+    sources and checkpoints are untouched)."""
+    w, idx = _case(name)
+    print(f"background window {name} {cfg}", flush=True)
+    ctx = open_ctx(w, q_max=len(idx), ckpt_interval=7 if cfg == "ckpt" else 0)
+    if cfg == "two-step":
+        ctx.set_tuning(*_bench_tuning())
+    elif cfg == "marching":
+        ctx.set_tuning(13, 1, 0, 1, 0)
+    for i in idx:
+        add_shot(ctx, w, i)
+    m32 = f32(w.m_true)
+    before = ctx.apply_born(m32)
+    got = split(w, idx, ctx.background_window())
+    prob = oracle_problem(w)
+    for k, i in enumerate(idx):
+        _, want = prob.background_shot(i, want_rec=True)
+        assert np.all(got[k][0] == 0)
+        assert rel(got[k], want) <= OP_TOL
+    after = ctx.apply_born(m32)
+    assert np.array_equal(before, after)
+    ctx.close()
