@@ -120,3 +120,20 @@ def test_3d_full_size_dot_product():
     err = abs(lhs - rhs) / abs(lhs)
     print(f"dot test: lhs {lhs:.9e} rhs {rhs:.9e} rel {err:.2e}", flush=True)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("ckpt", [0, 9])
+def test_3d_background_window_matches_oracle(case, ckpt):
+    """3-D finite-difference modelling (background wavefield at the
+    receivers, shots of different length, a deep and a repeated receiver)
+    against the oracle's."""
+    w, idx = case[0], case[1]
+    ctx = open_ctx(w, q_max=3, ckpt_interval=ckpt)
+    for i in idx:
+        add_shot(ctx, w, i)
+    got = split(w, idx, ctx.background_window())
+    prob = oracle_problem(w)
+    for k, i in enumerate(idx):
+        _, want = prob.background_shot(i, want_rec=True)
+        assert rel(got[k], want) <= OP_TOL
+    ctx.close()
