@@ -114,6 +114,8 @@ def parse():
                          "built-in default)")
     ap.add_argument("--cpu-sample-nt", type=int, default=3000)
     ap.add_argument("--cpu-sample-shots", type=int, default=2)
+    ap.add_argument("--cpu-sample-nt3d", type=int, default=100,
+                    help="3d workload: time steps of the oracle sample")
     ap.add_argument("--only-steps", action="store_true",
                     help="time the steps only (for profiler runs)")
     ap.add_argument("--workload", default="2d",
@@ -358,6 +360,29 @@ def bench_3d(args, P, synth, torch):
                                 round(pair / res["plain"] / 1e9, 3)}
                            if "plain" in res else None),
     }
+    if not args.no_cpu_baseline:
+        # the oracle on one shot at a bounded length (one Born and one
+        # adjoint application, FP64, OpenMP over the host cores)
+        import oracle
+        ns = args.cpu_sample_nt3d
+        s0 = w.shots[0]
+        shots = [synth.Shot(0, s0.src, s0.rec, ns, s0.f0)]
+        grid = oracle.Grid(3, w.nz, w.ny, w.nx, w.nb, w.h, w.dt)
+        prob = oracle.Problem(grid, vel.astype(np.float64), shots)
+        t = time.perf_counter()
+        d = prob.born_shot(0, w.m_true.astype(np.float32).astype(np.float64))
+        prob.adjoint_shot(0, d)
+        tc = time.perf_counter() - t
+        cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+        out["cpu_baseline"] = {
+            "value": round(2 * npad * (ns - 1) / tc / 1e9, 4),
+            "unit": "Gpt-updates/s",
+            "cores": cores,
+            "kind": "oracle",
+            "sample": f"1 shot, nt={ns} (of {nt}), one Born + one adjoint "
+                      f"application, FP64, {tc:.1f}s",
+        }
+        log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
 
