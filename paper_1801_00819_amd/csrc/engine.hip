@@ -578,10 +578,19 @@ int adjoint_segments(brls_ctx* c, const ShotDev* tab, int nsh, int pb,
   return BRLS_OK;
 }
 
+// Shots per adjoint work item. The two-step adjoint with 4 or 8 shots per
+// item runs cooperative blocks of that many wavefronts, one shot each (idle
+// where the window holds fewer), so the count is not clamped there.
+int adj_pb(const brls_ctx* c, int nsh) {
+  const int pb = c->adj_per_block;
+  if (two_step(c) && (pb == 4 || pb == 8)) return pb;
+  return std::min(pb, nsh);
+}
+
 int enqueue_adjoint(brls_ctx* c, int batched) {
   const int nsh = (int)c->order.size();
   const int ntm = nt_max_of(c, c->order);
-  const int pb = batched ? std::min(c->adj_per_block, nsh) : 1;
+  const int pb = batched ? adj_pb(c, nsh) : 1;
   const int ngroups = batched ? (nsh + pb - 1) / pb : 1;
   int rc;
   if ((rc = zero_fields(c))) return rc;
@@ -617,7 +626,7 @@ int run_op(brls_ctx* c, int op) {
   const int nsh = (int)c->order.size();
   const bool adj = op == kAdjoint;
   const GraphKey key(op, nsh,
-                     std::min(adj ? c->adj_per_block : c->per_block, nsh),
+                     adj ? adj_pb(c, nsh) : std::min(c->per_block, nsh),
                      c->variant, nt_max_of(c, c->order),
                      adj ? c->adj_resident_grid : c->resident_grid);
   auto it = c->graphs.find(key);

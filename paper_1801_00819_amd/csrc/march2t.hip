@@ -46,9 +46,15 @@ __device__ __forceinline__ bool core_entry(int le, int cz) {
          l < kLanes - kRadius;
 }
 
-template <int CZ, int AHEAD, int MODE, bool INT>
+// COOP (adjoint, cooperative blocks): the item is one shot, coop_shot, and
+// the image accumulators go to this wavefront's LDS slice `accl` ([CZ][64])
+// for the block to sum over its shots, instead of to the group's float64
+// accumulator.
+template <int CZ, int AHEAD, int MODE, bool INT, bool COOP = false>
 __device__ __forceinline__ void march2_item(const StepArgs& a, int t, int grp,
-                                            int z0, int x0, float* inj) {
+                                            int z0, int x0, float* inj,
+                                            float* accl = nullptr,
+                                            int coop_shot = 0) {
   constexpr bool BG = MODE == kBackground;
   constexpr bool BORN = MODE == kBorn;
   constexpr bool ADJ = MODE == kAdjoint;
@@ -81,8 +87,9 @@ __device__ __forceinline__ void march2_item(const StepArgs& a, int t, int grp,
   for (int j = 0; j < CZ; ++j) acc[j] = 0.f;
   bool any = false;
 
-  const int s0 = grp * a.per_block;
-  const int s1 = min(s0 + a.per_block, a.nshots);
+  const int s0 = COOP ? coop_shot : grp * a.per_block;
+  const int s1 =
+      COOP ? min(coop_shot + 1, a.nshots) : min(s0 + a.per_block, a.nshots);
   for (int s = s0; s < s1; ++s) {
     // the launch covers levels n and n + 1 (Born, background: input
     // levels) or k and k - 1 (adjoint: output levels), a.nsub of them
@@ -324,7 +331,12 @@ __device__ __forceinline__ void march2_item(const StepArgs& a, int t, int grp,
       (void)mo;
     }
   }
-  if (ADJ && any) {
+  if constexpr (COOP) {
+    if (ADJ) {
+#pragma unroll
+      for (int j = 0; j < CZ; ++j) accl[j * kLanes + lane] = acc[j];
+    }
+  } else if (ADJ && any) {
     double* out = a.acc + (int64_t)grp * mplane +
                   (int64_t)(z0 - g.nb) * g.nx + (xl - g.nb);
     int mo = 0, z = z0;
@@ -379,8 +391,89 @@ __global__ void __launch_bounds__(kLanes* kWaves) k_march2t(StepArgs a) {
   }
 }
 
+// Adjoint with cooperative blocks: the P wavefronts of a block march the P
+// shots of one group over the same tile, park their image accumulators in
+// LDS and the block adds their sum over the shots (in shot order, float64)
+// to the group's accumulator: one read-modify-write per point and launch
+// for P shots instead of P.
+template <int CZ, int AHEAD, int P>
+__global__ void __launch_bounds__(kLanes* P) k_march2t_coop(StepArgs a) {
+  __shared__ float inj_all[P * kLanes];
+  __shared__ float accs[P * CZ * kLanes];
+  const int wv = (int)uni((uint32_t)threadIdx.x / kLanes);
+  const int lane = threadIdx.x & (kLanes - 1);
+  float* inj = inj_all + wv * kLanes;
+  inj[lane] = 0.f;
+  const Geo2D& g = a.g;
+  const int mplane = g.nz * g.nx;
+  const int items = g.ntiles * a.ngroups;
+  int first, hi, stride;
+  if (a.resident_grid & 2) {
+    first = (int)blockIdx.x;
+    hi = items;
+    stride = (int)gridDim.x;
+  } else {
+    const int xcd = blockIdx.x & 7;
+    const int q = items >> 3, r = items & 7;
+    first = xcd * q + min(xcd, r) + (int)(blockIdx.x >> 3);
+    hi = xcd * q + min(xcd, r) + q + (xcd < r ? 1 : 0);
+    stride = (int)(gridDim.x >> 3);
+  }
+  for (int L = first; L < hi; L += stride) {
+    const int grp = L % a.ngroups;
+    const int tl = L / a.ngroups;
+    const int tzi = tl % g.ntz, txi = tl / g.ntz;
+    const int z0 = tzi * CZ;
+    const int x0 = g.x_org + txi * kCore;
+    const int t = tzi * g.ntx + txi;
+    const bool interior = x0 - kRadius >= g.nb &&
+                          x0 + kCore + kRadius <= g.nb + g.nx &&
+                          z0 - kRadius >= g.nb &&
+                          z0 + CZ + kRadius <= g.nb + g.nz;
+    float* accl = accs + wv * CZ * kLanes;
+    const int my_shot = grp * P + wv;
+    if (interior)
+      march2_item<CZ, AHEAD, kAdjoint, true, true>(a, t, grp, z0, x0, inj,
+                                                   accl, my_shot);
+    else
+      march2_item<CZ, AHEAD, kAdjoint, false, true>(a, t, grp, z0, x0, inj,
+                                                    accl, my_shot);
+    __syncthreads();
+    for (int e = threadIdx.x; e < CZ * kLanes; e += P * kLanes) {
+      const int j = e / kLanes, ln = e % kLanes;
+      const int xl = x0 - kRadius + ln, z = z0 + j;
+      if (ln >= kRadius && ln < kLanes - kRadius && xl >= g.nb &&
+          xl < g.nb + g.nx && z >= g.nb && z < g.nb + g.nz) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < P; ++w) sum += (double)accs[w * CZ * kLanes + e];
+        a.acc[(int64_t)grp * mplane + (int64_t)(z - g.nb) * g.nx +
+              (xl - g.nb)] += sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int CZ, int AHEAD, int P>
+static hipError_t launch_t2_coop(const StepArgs& a, hipStream_t st) {
+  static const int cap = resident_blocks(
+      reinterpret_cast<const void*>(&k_march2t_coop<CZ, AHEAD, P>),
+      kLanes * P);
+  const int need = a.g.ntiles * a.ngroups;
+  const int lim = (a.resident_grid & 1) ? cap : need;
+  const int nblk = ((need < lim ? need : lim) + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_march2t_coop<CZ, AHEAD, P>), dim3(nblk),
+                     dim3(kLanes * P), 0, st, a);
+  return hipGetLastError();
+}
+
 template <int CZ, int AHEAD, int MODE>
 static hipError_t launch_t2_mode(const StepArgs& a, hipStream_t st) {
+  if (MODE == kAdjoint && a.per_block == 4)
+    return launch_t2_coop<CZ, AHEAD, 4>(a, st);
+  if (MODE == kAdjoint && a.per_block == 8)
+    return launch_t2_coop<CZ, AHEAD, 8>(a, st);
   static const int cap = resident_blocks(
       reinterpret_cast<const void*>(&k_march2t<CZ, AHEAD, MODE>),
       kLanes * kWaves);

@@ -108,6 +108,33 @@ def test_every_tile_shape_matches_oracle(P, variant, ckpt):
     ctx.close()
 
 
+@pytest.mark.parametrize("apb", [4, 8])
+@pytest.mark.parametrize("variant", [17, 18])
+def test_cooperative_adjoint_matches_oracle(P, variant, apb):
+    """The two-step adjoint with 4 or 8 shots per work item runs cooperative
+    blocks, one wavefront per shot of a group and the shots' image
+    contributions summed in LDS: the ragged 3-shot window (idle wavefronts
+    in every block) against the oracle, each grid shape, batched and graph
+    launches."""
+    w, idx = _case("ragged2d")
+    print(f"cooperative adjoint variant={variant} shots/item={apb}",
+          flush=True)
+    ctx = open_ctx(w, q_max=3)
+    for i in idx:
+        add_shot(ctx, w, i)
+    prob = oracle_problem(w)
+    r = [f32(synth.gaussian((w.shots[i].nt, w.shots[i].nrec), 60 + i))
+         for i in idx]
+    rflat = np.concatenate([x.ravel() for x in r])
+    want = prob.adjoint([x.astype(np.float64) for x in r], idx)
+    for rg in (0, 1, 2):
+        ctx.set_tuning(variant, 1, 0, apb, rg)
+        for mode in (1, 2):
+            ctx.set_exec(mode)
+            assert rel(ctx.apply_adjoint(rflat), want) <= OP_TOL
+    ctx.close()
+
+
 def _dense_receivers():
     """Receivers at every column of two rows, each position twice, and one
     more row at the bottom of the model: more entries on a strip row than a
@@ -408,7 +435,7 @@ def test_full_size_kernel_forms_agree(P, big):
     out = {}
     for tune in ((0, 2, 1, 4, 0), (11, 1, 0, 2, 0), (12, 2, 1, 4, 0),
                  (13, 1, 0, 2, 0), (14, 1, 1, 2, 1), (17, 1, 0, 4, 2),
-                 (18, 2, 2, 2, 0)):
+                 (18, 2, 2, 2, 0), (18, 1, 0, 8, 0), (18, 1, 0, 4, 1)):
         print(f"512x1024 window, launch choice {tune}", flush=True)
         ctx.set_tuning(*tune)
         out[tune] = (ctx.apply_born(m).cpu().numpy(),
