@@ -47,9 +47,10 @@ __device__ __forceinline__ bool core_entry(int le, int cz) {
 }
 
 // COOP (adjoint, cooperative blocks): the item is one shot, coop_shot, and
-// the image accumulators go to this wavefront's LDS slice `accl` ([CZ][64])
-// for the block to sum over its shots, instead of to the group's float64
-// accumulator.
+// its image contributions accumulate in this wavefront's LDS slice `accl`
+// ([CZ][64], each lane its own column) for the block to sum over its shots,
+// instead of in registers flushed to the group's float64 accumulator (the
+// CZ registers saved raise the occupancy from 3 to 4 wavefronts per SIMD).
 template <int CZ, int AHEAD, int MODE, bool INT, bool COOP = false>
 __device__ __forceinline__ void march2_item(const StepArgs& a, int t, int grp,
                                             int z0, int x0, float* inj,
@@ -82,9 +83,13 @@ __device__ __forceinline__ void march2_item(const StepArgs& a, int t, int grp,
   const Rsrc Rw = rsrc(a.wp);
   const Rsrc Rp = rsrc(a.pm);
 
-  float acc[CZ];
+  float acc[COOP ? 1 : CZ];
 #pragma unroll
-  for (int j = 0; j < CZ; ++j) acc[j] = 0.f;
+  for (int j = 0; j < (COOP ? 1 : CZ); ++j) acc[j] = 0.f;
+  if constexpr (COOP) {
+#pragma unroll
+    for (int j = 0; j < CZ; ++j) accl[j * kLanes + lane] = 0.f;
+  }
   bool any = false;
 
   const int s0 = COOP ? coop_shot : grp * a.per_block;
@@ -267,7 +272,13 @@ __device__ __forceinline__ void march2_item(const StepArgs& a, int t, int grp,
         if (coreA) {
           if (BG && a.write_d2 && in && core_lane)
             bstore<kNT>(RdA, v_mod, mo, inc);
-          if (ADJ && in) acc[i - kRadius] = fmaf(-dA[i], un, acc[i - kRadius]);
+          if (ADJ && in) {
+            if constexpr (COOP)
+              accl[(i - kRadius) * kLanes + lane] =
+                  fmaf(-dA[i], un, accl[(i - kRadius) * kLanes + lane]);
+            else
+              acc[i - kRadius] = fmaf(-dA[i], un, acc[i - kRadius]);
+          }
           if (!two && okx && core_lane) {  // one step: A's rows are output
             bstore(Rvo, v_lane, so, vn);
             bstore(Ruo, v_lane, so, un);
@@ -325,18 +336,19 @@ __device__ __forceinline__ void march2_item(const StepArgs& a, int t, int grp,
             bstore(Rvo, v_lane, sob, vn);
             bstore(Ruo, v_lane, sob, un);
           }
-          if (ADJ && in) acc[i - 8] = fmaf(-dB[i], un, acc[i - 8]);
+          if (ADJ && in) {
+            if constexpr (COOP)
+              accl[(i - 8) * kLanes + lane] =
+                  fmaf(-dB[i], un, accl[(i - 8) * kLanes + lane]);
+            else
+              acc[i - 8] = fmaf(-dB[i], un, acc[i - 8]);
+          }
         }
       }
       (void)mo;
     }
   }
-  if constexpr (COOP) {
-    if (ADJ) {
-#pragma unroll
-      for (int j = 0; j < CZ; ++j) accl[j * kLanes + lane] = acc[j];
-    }
-  } else if (ADJ && any) {
+  if (!COOP && ADJ && any) {
     double* out = a.acc + (int64_t)grp * mplane +
                   (int64_t)(z0 - g.nb) * g.nx + (xl - g.nb);
     int mo = 0, z = z0;
