@@ -11,6 +11,11 @@ advances the background wavefield alongside the Born field, and the backward
 pass recomputes the background segment by segment from its checkpoints
 instead of keeping every time step. All computation runs in the HIP library;
 this module only passes device pointers.
+
+The same function differentiates the split-step Fourier pair: a
+device-pointer ``paper_1801_00819_amd.ssf.SsfContext`` has the same
+``apply_born`` / ``apply_adjoint`` (its data are the window's frequency-
+domain (re, im) pairs).
 """
 from __future__ import annotations
 
@@ -19,7 +24,8 @@ import torch
 
 class BornFn(torch.autograd.Function):
     """``d = BornFn.apply(m, ctx)`` with ``m`` a float32 CUDA tensor of the
-    model shape and ``ctx`` a device-pointer :class:`Context`."""
+    model shape and ``ctx`` a device-pointer :class:`Context` (or
+    split-step context)."""
 
     @staticmethod
     def forward(fctx, m: torch.Tensor, lib_ctx) -> torch.Tensor:

@@ -256,3 +256,29 @@ def test_full_size_dot_product(P, big):
     lhs = float(torch.dot(ctx.apply_born(m).double(), d.double()))
     rhs = float(torch.sum(m.double() * ctx.apply_adjoint(d).double()))
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_autograd_gradient_matches_oracle_adjoint(P):
+    """BornFn over the split-step context: the gradient of
+    0.5 ||A m - d||^2 against the oracle's A^T (A m - d)."""
+    import torch
+
+    from paper_1801_00819_amd.autograd import misfit
+    w = synth.ssf_small()
+    prob = _oracle(w)
+    ctx = _open(w, device=True)
+    for i, s in enumerate(w.shots):
+        ctx.update(i, s.xs, s.rec, s.f0)
+    d = [synth.gaussian((prob.nw, s.nrec, 2), 610 + i)
+         for i, s in enumerate(w.shots)]
+    dflat = f32(np.concatenate([x.ravel() for x in d]))
+    m0 = f32(0.5 * w.m_true)
+    m = torch.from_numpy(m0).cuda().requires_grad_(True)
+    loss = misfit(m, torch.from_numpy(dflat).cuda(), ctx)
+    loss.backward()
+    am = prob.born(m0.astype(np.float64), [0, 1, 2])
+    r = [a - dflat[lo:hi].reshape(x.shape).astype(np.float64)
+         for a, (x, lo, hi) in zip(am, _spans(d))]
+    want = prob.adjoint(r, [0, 1, 2])
+    assert rel(m.grad.cpu().numpy(), want) <= OP_TOL
+    ctx.close()
