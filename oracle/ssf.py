@@ -214,6 +214,16 @@ class SsfProblem:
             img += self.adjoint_shot(i, x[..., 0] + 1j * x[..., 1])
         return img
 
+    def illumination(self, idx: Sequence[int]) -> np.ndarray:
+        """Source-side illumination of a window: at each point, the sum over
+        its shots and frequencies of |W_j(x)|^2 (the diagonal of A^T A when
+        the receivers record every column of the level itself, with no
+        propagation between scatterer and receiver)."""
+        acc = np.zeros(self.grid.model_shape)
+        for i in idx:
+            acc += np.sum(np.abs(self.weights(i)) ** 2, axis=1)
+        return acc
+
     def observed(self, d_time: np.ndarray) -> np.ndarray:
         """Time-domain data (nt, nrec) of one shot to the operator's data
         space: (nw, nrec, 2) pairs of its DFT over the band."""

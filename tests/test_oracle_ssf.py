@@ -336,3 +336,22 @@ def test_source_field_is_the_2d_greens_function_below_the_source():
     assert np.max(amp[far]) <= 0.02 and np.max(ph[far]) <= 0.03
     assert np.max(amp[farther]) < np.max(amp[far])
     assert np.max(ph[farther]) < np.max(ph[far])
+
+
+def test_illumination_is_the_hessian_diagonal_on_one_level():
+    """One level, every column a receiver: A is diagonal per frequency, so
+    A^T A is diagonal and its diagonal is the illumination (brute force
+    over unit images); two shots sum."""
+    nx = 16
+    shots = [SsfShot(xs=5, rec=np.arange(nx), f0=15.0),
+             SsfShot(xs=11, rec=np.arange(nx), f0=15.0)]
+    p = _problem(_layered(1, nx, 7), dx=12.0, dz=12.0, nt=64, dt=4e-3,
+                 fmin=5.0, fmax=40.0, ntap=2, shots=shots)
+    H = np.zeros((nx, nx))
+    for k in range(nx):
+        e = np.zeros((1, nx))
+        e[0, k] = 1.0
+        H[:, k] = p.adjoint(p.born(e, [0, 1]), [0, 1]).ravel()
+    assert np.max(np.abs(H - np.diag(np.diag(H)))) <= 1e-14 * np.max(H)
+    assert np.max(np.abs(np.diag(H) - p.illumination([0, 1]).ravel())) \
+        <= 1e-13 * np.max(H)
