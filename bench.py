@@ -130,6 +130,11 @@ def parse():
                          "window configuration")
     ap.add_argument("--ssf-windows", type=int, default=0,
                     help="ssf workload: windows of the chain to run (0: all)")
+    ap.add_argument("--ssf-precond", type=int, default=0, choices=[0, 1],
+                    help="ssf workload: 1 = illumination-preconditioned CG")
+    ap.add_argument("--ssf-regularize", type=int, default=0, choices=[0, 1],
+                    help="ssf workload: 1 = damp the correction to the "
+                         "previous window's image")
     ap.add_argument("--ssf-data", default="nonlinear",
                     choices=["nonlinear", "born"],
                     help="ssf workload: finite-difference modelling in the "
@@ -787,6 +792,8 @@ def bench_ssf(args, P, synth, torch):
     lam = w.lam_rel * nrm
     # ---- the chain (timed) ---------------------------------------------
     c = open_ctx(lam)
+    c.set_precond(args.ssf_precond)
+    c.set_regularization(args.ssf_regularize)
     image = torch.empty(w.model_shape, dtype=torch.float32, device="cuda")
     held, lat, its = [], [], []
     torch.cuda.synchronize()
@@ -870,7 +877,11 @@ def bench_ssf(args, P, synth, torch):
                                + ("nonlinear FD data (true minus migration "
                                   "velocity, top-muted)" if nonlinear else
                                   "two-way FD Born data")
-                               + " + 1 % noise",
+                               + " + 1 % noise"
+                               + (", illumination preconditioner"
+                                  if args.ssf_precond else "")
+                               + (", correction-regularised recursion"
+                                  if args.ssf_regularize else ""),
                    "model": [nz, nx]},
         "s_per_window": {"mean": round(float(np.mean(lat)), 4),
                          "p50": round(float(np.percentile(lat, 50)), 4),

@@ -129,6 +129,27 @@ int brls_ssf_observed(brls_ssf_ctx* ctx, float* d_out);
 int brls_ssf_solve_window(brls_ssf_ctx* ctx, int32_t max_iter, double rtol,
                           brls_stats* stats);
 
+/* Preconditioner of the window CG (the paper asks each window for one,
+ * after eq. 11, and names none): 0 none (default); 1 the diagonal
+ * M = I + 0.01 mean(I), I the window's source illumination (below), the
+ * search directions following M^{-1} s; the stop test stays on ||s||.
+ * Other modes: BRLS_EINVAL. */
+int brls_ssf_set_precond(brls_ssf_ctx* ctx, int32_t mode);
+int brls_ssf_get_precond(const brls_ssf_ctx* ctx, int32_t* mode);
+
+/* The window's source illumination [nz][nx]: at each point the sum over its
+ * shots and frequencies of |W_j(x)|^2 (the diagonal of A^T A were the
+ * receivers recording every column of the scatterer's own level).
+ * out: host or device per flags. */
+int brls_ssf_illumination(brls_ssf_ctx* ctx, float* out);
+
+/* Damping of each window's solve (eq. 10, and the two readings of eq. 11):
+ * 0 (default) lambda ||m||^2; 1 lambda ||m - m_start||^2, m_start the
+ * image the solve starts from (the previous window's), which keeps the
+ * memory of earlier windows. Other modes: BRLS_EINVAL. */
+int brls_ssf_set_regularization(brls_ssf_ctx* ctx, int32_t mode);
+int brls_ssf_get_regularization(const brls_ssf_ctx* ctx, int32_t* mode);
+
 /* Copy the current image out / set it (the next solve starts there). */
 int brls_ssf_image(brls_ssf_ctx* ctx, float* out);
 int brls_ssf_set_image(brls_ssf_ctx* ctx, const float* m);

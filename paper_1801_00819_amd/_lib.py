@@ -148,6 +148,12 @@ SIGNATURES = [
     ("brls_ssf_observed", _I32, [_VP, _VP]),
     ("brls_ssf_solve_window", _I32, [_VP, _I32, ctypes.c_double,
                                      ctypes.POINTER(brls_stats)]),
+    ("brls_ssf_set_precond", _I32, [_VP, _I32]),
+    ("brls_ssf_get_precond", _I32, [_VP, ctypes.POINTER(ctypes.c_int32)]),
+    ("brls_ssf_illumination", _I32, [_VP, _VP]),
+    ("brls_ssf_set_regularization", _I32, [_VP, _I32]),
+    ("brls_ssf_get_regularization", _I32,
+     [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_ssf_image", _I32, [_VP, _VP]),
     ("brls_ssf_set_image", _I32, [_VP, _VP]),
     ("brls_ssf_kernel_timing", _I32, [_VP, _I32]),

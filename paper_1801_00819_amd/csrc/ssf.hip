@@ -514,6 +514,24 @@ __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_adjoint(
   }
 }
 
+// out[p] = sum over the window's shots and frequencies of |W(p)|^2, in
+// double and in a fixed order (one thread per point).
+__global__ __launch_bounds__(256) void k_ssf_illumination(SsfArgs a,
+                                                          int64_t npts,
+                                                          float* out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  double acc = 0.0;
+  for (int i = 0; i < a.nshots; ++i) {
+    const float2* Wb = a.W + (int64_t)a.tab[i].slot * a.nw * npts + p;
+    for (int k = 0; k < a.nw; ++k) {
+      const float2 v = Wb[(int64_t)k * npts];
+      acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+  }
+  out[p] = (float)acc;
+}
+
 // Phase tables of every (frequency, level, column): the wavenumber-domain
 // factor divided by N, and the split-step factor times the taper, each
 // formed from its angle in double and rounded once to float.
@@ -677,6 +695,15 @@ hipError_t launch_ssf_tables(const SsfArgs& a, float2* ptab, float2* sstab,
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 16);
   hipLaunchKernelGGL(k_ssf_tables, dim3((unsigned)blocks), dim3(256), 0, st,
                      a, n, ptab, sstab);
+  return hipGetLastError();
+}
+
+hipError_t launch_ssf_illumination(const SsfArgs& a, float* out,
+                                   hipStream_t st) {
+  const int64_t npts = (int64_t)a.nz << a.log2n;
+  if (npts <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ssf_illumination, dim3((npts + 255) / 256), dim3(256),
+                     0, st, a, npts, out);
   return hipGetLastError();
 }
 

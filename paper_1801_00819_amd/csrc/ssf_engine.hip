@@ -74,6 +74,9 @@ struct brls_ssf_ctx {
   float* part = nullptr;
   float *m = nullptr, *p = nullptr, *s = nullptr, *gbuf = nullptr,
         *min = nullptr;
+  int precond = 0;     // 1: diagonal illumination preconditioner
+  int regularize = 0;  // 1: damp the correction to the starting image
+  float *minv = nullptr, *z = nullptr, *dm = nullptr;
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr,
         *dtime = nullptr;
   double *partial = nullptr, *scal = nullptr;
@@ -234,6 +237,31 @@ int adjoint_of(brls_ssf_ctx* c, const float* d_dev) {
   return timed_end(c, &t);
 }
 
+// Stabiliser of the illumination preconditioner, relative to its mean.
+constexpr double kIllumEps = 0.01;
+
+int window_illumination(brls_ssf_ctx* c, float* out) {
+  int rc;
+  if ((rc = ensure_tab(c))) return rc;
+  SCHECK(c, launch_ssf_illumination(c->args, out, c->st));
+  return BRLS_OK;
+}
+
+// minv = 1 / (I + kIllumEps * mean(I)), I the window illumination.
+int build_minv(brls_ssf_ctx* c) {
+  int rc;
+  if ((rc = window_illumination(c, c->minv))) return rc;
+  SCHECK(c, launch_sum(c->minv, c->M, c->partial, c->scal, c->st));
+  double sum = 0.0;
+  if ((rc = read_scalars(c, &sum, 1))) return rc;
+  const double shift = kIllumEps * sum / (double)c->M;
+  if (!(shift > 0.0))
+    return sfail(c, BRLS_EBREAKDOWN,
+                 "preconditioner: the window's shots illuminate nothing");
+  SCHECK(c, launch_recip_shift(c->minv, c->minv, shift, c->M, c->st));
+  return BRLS_OK;
+}
+
 int64_t shot_floats(const brls_ssf_ctx* c, int slot) {
   return 2LL * c->nw * c->slots[slot].nrec;
 }
@@ -391,6 +419,8 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
       (rc = salloc(c, &c->part, items * M)) || (rc = salloc(c, &c->m, M)) ||
       (rc = salloc(c, &c->p, M)) || (rc = salloc(c, &c->s, M)) ||
       (rc = salloc(c, &c->gbuf, M)) || (rc = salloc(c, &c->min, M)) ||
+      (rc = salloc(c, &c->minv, M)) || (rc = salloc(c, &c->z, M)) ||
+      (rc = salloc(c, &c->dm, M)) ||
       (rc = salloc(c, &c->dobs, D)) || (rc = salloc(c, &c->r, D)) ||
       (rc = salloc(c, &c->q, D)) || (rc = salloc(c, &c->dscr, D)) ||
       (rc = salloc(c, &c->dtime, (int64_t)g.nt * g.nrec_max)) ||
@@ -647,17 +677,22 @@ int brls_ssf_solve_window(brls_ssf_ctx* c, int32_t max_iter, double rtol,
   const int64_t M = c->M, D = (int64_t)c->g.q_max * c->seg;
   double sc[2];
   int rc;
-  // r = d - A m; s = A^T r - lambda m; gamma = ||s||^2
+  // r = d - A m; s = A^T r - lambda m (correction mode: - lambda (m -
+  // m_start)); gamma = ||s||^2
+  const bool corr = c->regularize == 1;
+  if (corr) SCHECK(c, launch_fill_f32(c->dm, M, 0.f, c->st));
+  const float* damped = corr ? c->dm : c->m;
   if ((rc = born_of(c, c->m))) return finish(rc);
   SCHECK(c, launch_sub(c->r, c->dobs, c->q, D, c->st));
   if ((rc = adjoint_of(c, c->r))) return finish(rc);
-  SCHECK(c, launch_grad_norm(c->s, c->gbuf, c->m, lam, M, c->partial,
+  SCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                              c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
   double gamma = sc[0];
   if (!std::isfinite(gamma))
     return finish(sfail(c, BRLS_ENONFINITE, "non-finite gradient norm"));
   st.s0_norm = st.s_norm = std::sqrt(gamma);
+  double snorm = st.s0_norm;
   double ref = 0.0;
   if (rtol > 0) {
     if ((rc = adjoint_of(c, c->dobs))) return finish(rc);
@@ -666,11 +701,21 @@ int brls_ssf_solve_window(brls_ssf_ctx* c, int32_t max_iter, double rtol,
     ref = std::sqrt(sc[0]);
     st.ref_norm = ref;
   }
-  SCHECK(c, hipMemcpyAsync(c->p, c->s, M * 4, hipMemcpyDeviceToDevice,
-                           c->st));
+  // preconditioned form: directions follow z = M^{-1} s and gamma =
+  // <s, z>; the stop test stays on ||s||
+  const bool pre = c->precond != 0;
+  if (pre) {
+    if ((rc = build_minv(c))) return finish(rc);
+    SCHECK(c, launch_mul(c->z, c->minv, c->s, M, c->st));
+    SCHECK(c, launch_dot(c->s, c->z, M, c->partial, c->scal, c->st));
+    if ((rc = read_scalars(c, sc, 1))) return finish(rc);
+    gamma = sc[0];
+  }
+  SCHECK(c, hipMemcpyAsync(c->p, pre ? c->z : c->s, M * 4,
+                           hipMemcpyDeviceToDevice, c->st));
   for (int it = 0; it < max_iter; ++it) {
     if (gamma == 0.0) break;
-    if (rtol > 0 && std::sqrt(gamma) <= rtol * ref) break;
+    if (rtol > 0 && snorm <= rtol * ref) break;
     if ((rc = born_of(c, c->p))) return finish(rc);
     SCHECK(c, launch_dot(c->q, c->q, D, c->partial, c->scal, c->st));
     SCHECK(c, launch_dot(c->p, c->p, M, c->partial, c->scal + 1, c->st));
@@ -683,23 +728,67 @@ int brls_ssf_solve_window(brls_ssf_ctx* c, int32_t max_iter, double rtol,
                           delta));
     const double alpha = gamma / delta;
     SCHECK(c, launch_axpy(c->m, c->p, alpha, M, c->st));
+    if (corr) SCHECK(c, launch_axpy(c->dm, c->p, alpha, M, c->st));
     SCHECK(c, launch_axpy(c->r, c->q, -alpha, D, c->st));
     if ((rc = adjoint_of(c, c->r))) return finish(rc);
-    SCHECK(c, launch_grad_norm(c->s, c->gbuf, c->m, lam, M, c->partial,
+    SCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                                c->scal, c->st));
-    if ((rc = read_scalars(c, sc, 1))) return finish(rc);
-    if (!std::isfinite(sc[0]))
+    if (pre) {
+      SCHECK(c, launch_mul(c->z, c->minv, c->s, M, c->st));
+      SCHECK(c, launch_dot(c->s, c->z, M, c->partial, c->scal + 1, c->st));
+    }
+    if ((rc = read_scalars(c, sc, pre ? 2 : 1))) return finish(rc);
+    const double gnew = pre ? sc[1] : sc[0];
+    if (!std::isfinite(sc[0]) || !std::isfinite(gnew))
       return finish(sfail(c, BRLS_ENONFINITE, "non-finite gradient norm"));
-    const double beta = sc[0] / gamma;
-    SCHECK(c, launch_xpby(c->p, c->s, beta, M, c->st));
-    gamma = sc[0];
+    const double beta = gnew / gamma;
+    SCHECK(c, launch_xpby(c->p, pre ? c->z : c->s, beta, M, c->st));
+    gamma = gnew;
+    snorm = std::sqrt(sc[0]);
     st.iters = it + 1;
-    st.s_norm = std::sqrt(gamma);
+    st.s_norm = snorm;
   }
   SCHECK(c, launch_dot(c->r, c->r, D, c->partial, c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
   st.r_norm = std::sqrt(sc[0]);
   return finish(BRLS_OK);
+}
+
+int brls_ssf_set_precond(brls_ssf_ctx* c, int32_t mode) {
+  if (!c) return BRLS_EINVAL;
+  if (mode != 0 && mode != 1)
+    return sfail(c, BRLS_EINVAL, "preconditioner mode %d: 0 or 1", mode);
+  c->precond = mode;
+  return BRLS_OK;
+}
+
+int brls_ssf_get_precond(const brls_ssf_ctx* c, int32_t* mode) {
+  if (!c || !mode) return BRLS_EINVAL;
+  *mode = c->precond;
+  return BRLS_OK;
+}
+
+int brls_ssf_set_regularization(brls_ssf_ctx* c, int32_t mode) {
+  if (!c) return BRLS_EINVAL;
+  if (mode != 0 && mode != 1)
+    return sfail(c, BRLS_EINVAL, "regularization mode %d: 0 or 1", mode);
+  c->regularize = mode;
+  return BRLS_OK;
+}
+
+int brls_ssf_get_regularization(const brls_ssf_ctx* c, int32_t* mode) {
+  if (!c || !mode) return BRLS_EINVAL;
+  *mode = c->regularize;
+  return BRLS_OK;
+}
+
+int brls_ssf_illumination(brls_ssf_ctx* c, float* out) {
+  if (!c || !out) return sfail(c, BRLS_EINVAL, "NULL argument");
+  int rc;
+  if ((rc = window_illumination(c, c->gbuf))) return rc;
+  SCHECK(c, hipMemcpyAsync(out, c->gbuf, c->M * 4, out_kind(c), c->st));
+  if (!dev_ptrs(c)) SCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
 }
 
 int brls_ssf_image(brls_ssf_ctx* c, float* out) {

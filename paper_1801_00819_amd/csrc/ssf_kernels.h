@@ -52,6 +52,10 @@ hipError_t launch_ssf_born(const SsfArgs& a, const float* m, float* d,
 // Per-(shot, frequency) image contributions of A^T d, [items][nz][nx].
 hipError_t launch_ssf_adjoint(const SsfArgs& a, const float* d, float* part,
                               hipStream_t st);
+// out = the window's source illumination: sum over its shots and
+// frequencies of |W_j(x)|^2 (float64 sums, fixed order).
+hipError_t launch_ssf_illumination(const SsfArgs& a, float* out,
+                                   hipStream_t st);
 // img = sum over items of part in a fixed order (npts a multiple of 4;
 // psum: kSsfSumGroups * npts doubles of scratch).
 constexpr int kSsfSumGroups = 16;

@@ -147,6 +147,42 @@ class SsfContext:
 
     solve_window = brls_ssf_solve_window
 
+    def brls_ssf_set_precond(self, mode: int):
+        """0: plain CG; 1: diagonal illumination preconditioner."""
+        self._check(L.lib().brls_ssf_set_precond(self._h, int(mode)))
+
+    set_precond = brls_ssf_set_precond
+
+    def brls_ssf_get_precond(self) -> int:
+        v = ctypes.c_int32()
+        self._check(L.lib().brls_ssf_get_precond(self._h, ctypes.byref(v)))
+        return v.value
+
+    get_precond = brls_ssf_get_precond
+
+    def brls_ssf_illumination(self, out=None):
+        out = self._model_out(out)
+        self._check(L.lib().brls_ssf_illumination(self._h,
+                                                  _ptr(out, self.device)))
+        return out
+
+    illumination = brls_ssf_illumination
+
+    def brls_ssf_set_regularization(self, mode: int):
+        """0: damp the image; 1: damp the correction to the image the solve
+        starts from (correction-regularised recursion)."""
+        self._check(L.lib().brls_ssf_set_regularization(self._h, int(mode)))
+
+    set_regularization = brls_ssf_set_regularization
+
+    def brls_ssf_get_regularization(self) -> int:
+        v = ctypes.c_int32()
+        self._check(L.lib().brls_ssf_get_regularization(self._h,
+                                                        ctypes.byref(v)))
+        return v.value
+
+    get_regularization = brls_ssf_get_regularization
+
     def brls_ssf_image(self, out=None):
         out = self._model_out(out)
         self._check(L.lib().brls_ssf_image(self._h, _ptr(out, self.device)))

@@ -162,6 +162,67 @@ def test_window_chain_matches_oracle(P, device):
     ctx.close()
 
 
+def test_illumination_matches_oracle(P):
+    """Source illumination of a three-shot window (sum over shots and
+    frequencies of |W_j|^2) against the oracle's, which is pinned as the
+    diagonal of A^T A."""
+    w = synth.ssf_small()
+    prob = _oracle(w)
+    ctx = _open(w)
+    for i, s in enumerate(w.shots):
+        ctx.update(i, s.xs, s.rec, s.f0)
+    got = ctx.illumination()
+    ref = prob.illumination(range(len(w.shots)))
+    print(f"illumination rel {rel(got, ref):.2e}")
+    assert rel(got, ref) <= OP_TOL
+    assert np.all(got > 0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precond,regularize", [(1, 0), (0, 1), (1, 1)])
+def test_solver_options_match_oracle(P, precond, regularize):
+    """The window chain with the illumination preconditioner, the
+    correction-regularised damping, and both, against the oracle's CG with
+    the same minv and m_ref."""
+    import oracle
+    w = synth.ssf_small()
+    prob = _oracle(w)
+    xt = [_time_data(w, i, 820 + i) for i in range(3)]
+    data = [prob.observed(x.astype(np.float64)) for x in xt]
+    lam = w.lam_rel * oracle.power_norm(prob, w.windows()[0], 20, seed=3)
+    m = None
+    for win in w.windows():
+        minv = (oracle.illumination_minv(prob.illumination(win))
+                if precond else None)
+        res = oracle.cgls(prob, win, [data[i] for i in win], lam, w.niter,
+                          m0=m, minv=minv,
+                          m_ref=m if regularize else None)
+        m = res.m
+    ctx = _open(w, q_max=2, lam=lam)
+    ctx.set_precond(precond)
+    ctx.set_regularization(regularize)
+    assert ctx.get_precond() == precond
+    assert ctx.get_regularization() == regularize
+    held = []
+    for win in w.windows():
+        for i in list(held):
+            if i not in win:
+                ctx.downdate(i)
+                held.remove(i)
+        for i in win:
+            if i not in held:
+                s = w.shots[i]
+                ctx.update(i, s.xs, s.rec, s.f0, xt[i])
+                held.append(i)
+        st = ctx.solve_window(w.niter)
+        assert st["iters"] == w.niter
+    img = ctx.image()
+    print(f"precond {precond} regularize {regularize} rel "
+          f"{rel(img, m):.2e}")
+    assert rel(img, m) <= IMG_TOL
+    ctx.close()
+
+
 def test_errors(P):
     w = synth.ssf_small()
     ctx = _open(w, q_max=2)
@@ -188,6 +249,14 @@ def test_errors(P):
     with pytest.raises(P.BrlsError) as e:
         ctx.downdate(99)
     assert e.value.code == -4
+    for bad_mode in (-1, 2):
+        with pytest.raises(P.BrlsError) as e:
+            ctx.set_precond(bad_mode)
+        assert e.value.code == -1
+        with pytest.raises(P.BrlsError) as e:
+            ctx.set_regularization(bad_mode)
+        assert e.value.code == -1
+    assert ctx.get_precond() == 0 and ctx.get_regularization() == 0
     ctx.downdate(7)
     ctx.downdate(8)
     st = ctx.solve_window(3)  # empty window: nothing to do
