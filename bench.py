@@ -66,9 +66,9 @@ TRAFFIC_2D = {
 # WRITE_SIZE x 1.000, the factors a 512 MiB device copy reads in the same
 # program), valid for the kernel sources of that hash.
 TRAFFIC_SSF = {
-    "sources_sha256_16": "cf5ada9dabb0aa96",
-    "born": 2 * 1204829.1 * 1024 + 566.2 * 1024,
-    "adjoint": 2 * 1519524.4 * 1024 + 773120.0 * 1024,
+    "sources_sha256_16": "4b5947b7cad94a2a",
+    "born": 2 * 1187398.6 * 1024 + 566.2 * 1024,
+    "adjoint": 2 * 1496217.3 * 1024 + 773120.0 * 1024,
 }
 
 
@@ -111,6 +111,9 @@ def parse():
                     help="stream workload: windows run with plain launches")
     ap.add_argument("--fr-windows", type=int, default=3,
                     help="windows solved to a fixed residual (0: skip)")
+    ap.add_argument("--no-host-window", action="store_true",
+                    help="skip the window solved through host pointers "
+                         "(PCIe-inclusive rate)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch choice by timing (else the "
                          "built-in default)")
@@ -229,6 +232,45 @@ def fixed_residual(args, P, w, data, lam, vel, torch):
             "plain_over_graph_first_window":
                 round(p[0]["wall"] / g[0]["wall"], 3),
             "graph_illumination_preconditioned": summary(pc)}
+
+
+def host_window(args, P, w, data, lam, vel, torch):
+    """The first window solved by a context that takes host pointers: the
+    window's data leave host memory inside brls_update (one copy per shot)
+    and the image returns to host memory. Timed from the first update to
+    the image on the host, against the same window through device
+    pointers."""
+    nrec = w.shots[0].nrec
+    win = w.windows()[0]
+    host = {i: data[i].cpu().numpy() for i in win}
+    npad = (w.nz + 2 * w.nb) * (w.nx + 2 * w.nb)
+    res = {}
+    for device in (False, True):
+        ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, w.nt, nrec, w.Q, w.h, w.dt,
+                          lam, vel, device=device)
+        ctx.set_tuning(*DEFAULT_TUNING)
+        ctx.set_exec(P.BRLS_EXEC_GRAPH)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in win:
+            s = w.shots[i]
+            ctx.update(i, s.src, s.rec, s.nt, s.f0,
+                       data[i] if device else host[i])
+        st = ctx.solve_window(args.iters)
+        img = ctx.image()
+        if device:
+            torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        ctx.close()
+        ups = 2 * (1 + st["iters"]) * len(win) * npad * (w.nt - 1)
+        res["host" if not device else "device"] = {
+            "seconds": round(sec, 4),
+            "Gpt_updates_per_s": round(ups / sec / 1e9, 2)}
+        del img
+    res["host_over_device"] = round(res["host"]["seconds"]
+                                    / res["device"]["seconds"], 4)
+    res["h2d_bytes"] = int(sum(host[i].nbytes for i in win))
+    return res
 
 
 def ops_only(P, w, vel, m_true):
@@ -1182,6 +1224,12 @@ def main():
         out["fixed_residual"] = fixed_residual(args, P, w, data, lam, vel,
                                                torch)
         log(f"fixed residual: {out['fixed_residual']}")
+
+    # ---- one window through host pointers (PCIe-inclusive) --------------
+    if not args.no_host_window:
+        out["host_pointers"] = host_window(args, P, w, data, lam, vel,
+                                           torch)
+        log(f"host pointers: {out['host_pointers']}")
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample -------------
     if not args.no_cpu_baseline:

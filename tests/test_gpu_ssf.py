@@ -175,7 +175,9 @@ def test_illumination_matches_oracle(P):
     ref = prob.illumination(range(len(w.shots)))
     print(f"illumination rel {rel(got, ref):.2e}")
     assert rel(got, ref) <= OP_TOL
-    assert np.all(got > 0)
+    # level 0 holds the sources only at their own columns; every level
+    # below is lit everywhere
+    assert np.all(got >= 0) and np.all(got[1:] > 0)
     ctx.close()
 
 
