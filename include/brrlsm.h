@@ -115,7 +115,9 @@ typedef struct {
  * null stream itself).
  * Checks CFL stability of the scheme (v_max dt / h below 0.5546 in 2-D and
  * 0.4529 in 3-D for the 8th-order stencil) and returns BRLS_EINVAL
- * otherwise.
+ * otherwise. Also BRLS_EINVAL: a padded grid (or its wavefield storage) of
+ * 2^29 points or more in 2-D, 2^30 in 3-D (the kernels' 32-bit byte
+ * offsets), or nt_max * nrec_max above 2^30.
  * Allocates the device state for q_max shots (see brls_memory_bytes). */
 int brls_open(const brls_grid* g, const float* vel, void* stream,
               brls_ctx** out);

@@ -82,7 +82,8 @@ typedef struct {
 
 /* Create a context. g: copied. vel: host [nz][nx] velocity (m/s), all > 0.
  * stream: hipStream_t to order work on, or NULL for a private stream.
- * Errors: BRLS_EINVAL (sizes, band, taper), BRLS_ENOMEM, BRLS_EDEVICE. */
+ * Errors: BRLS_EINVAL (sizes, band, taper; nz * nx or nt * nrec_max of
+ * 2^30 or more), BRLS_ENOMEM, BRLS_EDEVICE. */
 int brls_ssf_open(const brls_ssf_grid* g, const float* vel, void* stream,
                   brls_ssf_ctx** out);
 void brls_ssf_close(brls_ssf_ctx* ctx);

@@ -30,19 +30,32 @@ __all__ = [
 ]
 
 
-def _ptr(a, device: bool):
+def _ptr(a, device: bool, n: Optional[int] = None):
+    """Pointer to a float32 buffer the library reads or writes: a contiguous
+    CUDA tensor (device context) or a C-contiguous ndarray (host context)
+    holding at least ``n`` floats."""
     if a is None:
         return None
     if device:
-        if not (hasattr(a, "is_cuda") and a.is_cuda):
+        import torch
+        if not (isinstance(a, torch.Tensor) and a.is_cuda):
             raise TypeError("device context: pass a CUDA tensor")
+        if a.dtype != torch.float32:
+            raise TypeError(f"tensor must be float32, got {a.dtype}")
         if not a.is_contiguous():
             raise ValueError("tensor must be contiguous")
-        return ctypes.c_void_p(a.data_ptr())
-    if not (isinstance(a, np.ndarray) and a.dtype == np.float32
-            and a.flags.c_contiguous):
-        raise TypeError("host context: pass a C-contiguous float32 ndarray")
-    return ctypes.c_void_p(a.ctypes.data)
+        size = a.numel()
+        ptr = a.data_ptr()
+    else:
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float32
+                and a.flags.c_contiguous):
+            raise TypeError("host context: pass a C-contiguous float32 "
+                            "ndarray")
+        size = a.size
+        ptr = a.ctypes.data
+    if n is not None and size < n:
+        raise ValueError(f"buffer holds {size} floats, the call needs {n}")
+    return ctypes.c_void_p(ptr)
 
 
 class Context:
@@ -51,8 +64,10 @@ class Context:
     def __init__(self, handle, nz, ny, nx, device):
         self._h = handle
         self.model_shape = (nz, ny, nx)
+        self.model_size = nz * ny * nx
         self.device = device
         self._keep = []
+        self._data_size = {}  # shot id -> nt * nrec
 
     # ------------------------------------------------------------------
     def close(self):
@@ -81,22 +96,25 @@ class Context:
         sh.rec = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         if data is not None and not self.device:
             data = np.ascontiguousarray(data, dtype=np.float32)
-        p = _ptr(data, self.device)
+        p = _ptr(data, self.device, sh.nt * sh.nrec)
         sh.data = p.value if p is not None else None
         self._check(L.lib().brls_update(self._h, ctypes.byref(sh)))
+        self._data_size[int(id)] = sh.nt * sh.nrec
 
     update = brls_update
 
     def brls_downdate(self, id: int):
         self._check(L.lib().brls_downdate(self._h, int(id)))
+        self._data_size.pop(int(id), None)
 
     downdate = brls_downdate
 
     def brls_set_data(self, id: int, data):
         if not self.device:
             data = np.ascontiguousarray(data, dtype=np.float32)
-        self._check(L.lib().brls_set_data(self._h, int(id),
-                                          _ptr(data, self.device)))
+        self._check(L.lib().brls_set_data(
+            self._h, int(id),
+            _ptr(data, self.device, self._data_size.get(int(id)))))
 
     set_data = brls_set_data
 
@@ -138,7 +156,8 @@ class Context:
 
     def brls_image(self, out=None):
         out = self._model_out(out)
-        self._check(L.lib().brls_image(self._h, _ptr(out, self.device)))
+        self._check(L.lib().brls_image(self._h, _ptr(out, self.device,
+                                                      self.model_size)))
         return out
 
     image = brls_image
@@ -146,7 +165,8 @@ class Context:
     def brls_set_image(self, m):
         if not self.device:
             m = np.ascontiguousarray(m, dtype=np.float32)
-        self._check(L.lib().brls_set_image(self._h, _ptr(m, self.device)))
+        self._check(L.lib().brls_set_image(self._h, _ptr(m, self.device,
+                                                          self.model_size)))
 
     set_image = brls_set_image
 
@@ -180,8 +200,8 @@ class Context:
 
     def brls_illumination(self, out=None):
         out = self._model_out(out)
-        self._check(L.lib().brls_illumination(self._h,
-                                              _ptr(out, self.device)))
+        self._check(L.lib().brls_illumination(
+            self._h, _ptr(out, self.device, self.model_size)))
         return out
 
     illumination = brls_illumination
@@ -196,8 +216,9 @@ class Context:
                 out = torch.empty(n, dtype=torch.float32, device="cuda")
             else:
                 out = np.empty(n, dtype=np.float32)
-        self._check(L.lib().brls_apply_born(self._h, _ptr(m, self.device),
-                                            _ptr(out, self.device)))
+        self._check(L.lib().brls_apply_born(
+            self._h, _ptr(m, self.device, self.model_size),
+            _ptr(out, self.device, n)))
         return out
 
     apply_born = brls_apply_born
@@ -206,8 +227,9 @@ class Context:
         if not self.device:
             d = np.ascontiguousarray(d, dtype=np.float32)
         out = self._model_out(out)
-        self._check(L.lib().brls_apply_adjoint(self._h, _ptr(d, self.device),
-                                               _ptr(out, self.device)))
+        self._check(L.lib().brls_apply_adjoint(
+            self._h, _ptr(d, self.device, self.window_data_size()),
+            _ptr(out, self.device, self.model_size)))
         return out
 
     apply_adjoint = brls_apply_adjoint
@@ -223,8 +245,8 @@ class Context:
                 out = torch.empty(n, dtype=torch.float32, device="cuda")
             else:
                 out = np.empty(n, dtype=np.float32)
-        self._check(L.lib().brls_background_window(self._h,
-                                                   _ptr(out, self.device)))
+        self._check(L.lib().brls_background_window(
+            self._h, _ptr(out, self.device, n)))
         return out
 
     background_window = brls_background_window
@@ -337,6 +359,9 @@ def brls_open(ndim: int, nz: int, ny: int, nx: int, nb: int, nt_max: int,
         import torch
         stream = torch.cuda.current_stream().cuda_stream
     v = np.ascontiguousarray(vel, dtype=np.float32)
+    if v.size < nz * (ny if ndim == 3 else 1) * nx:
+        raise ValueError(f"vel holds {v.size} values, the grid has "
+                         f"{nz * (ny if ndim == 3 else 1) * nx} points")
     h_ = ctypes.c_void_p()
     rc = L.lib().brls_open(ctypes.byref(g), v.ctypes.data,
                            ctypes.c_void_p(stream) if stream else None,

@@ -723,10 +723,21 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
       g.nrec_max < 1 || g.q_max < 1 || !(g.h > 0) || !(g.dt > 0) ||
       !(g.lambda >= 0))
     return fail(nullptr, BRLS_EINVAL, "invalid grid sizes or spacing");
+  // The kernels address one wavefield, the model and a frame with 32-bit
+  // byte offsets (signed in 2-D, element index times four in 3-D), and one
+  // shot's data segment with 32-bit indices.
+  const int64_t lim = g.ndim == 2 ? ((int64_t)1 << 29) : ((int64_t)1 << 30);
   const int64_t mpts = (int64_t)g.nz * ny * g.nx;
-  if (mpts >= ((int64_t)1 << 30))
-    return fail(nullptr, BRLS_EINVAL, "model of %lld points is too large",
-                (long long)mpts);
+  const int64_t ppts = (int64_t)(g.nz + 2 * g.nb) *
+                       (g.ndim == 3 ? ny + 2 * g.nb : 1) * (g.nx + 2 * g.nb);
+  if (mpts >= lim || ppts >= lim)
+    return fail(nullptr, BRLS_EINVAL,
+                "padded grid of %lld points is too large (limit %lld)",
+                (long long)ppts, (long long)lim);
+  if ((int64_t)g.nt_max * g.nrec_max > ((int64_t)1 << 30))
+    return fail(nullptr, BRLS_EINVAL,
+                "nt_max * nrec_max = %lld exceeds 2^30 samples per shot",
+                (long long)g.nt_max * g.nrec_max);
   double vmax = 0.0;
   for (int64_t i = 0; i < mpts; ++i) {
     if (!(vel[i] > 0.f) || !std::isfinite(vel[i]))
@@ -825,9 +836,13 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   else
     c->ckpt_k = g.ckpt_interval;
   if (c->ckpt_k) c->nseg_max = (g.nt_max - 1 + c->ckpt_k - 1) / c->ckpt_k;
-  c->seg = round_up((int)std::min<int64_t>((int64_t)g.nt_max * g.nrec_max,
-                                           (int64_t)1 << 30),
-                    64);
+  if (c->fs >= lim) {  // the storage ring and pitch padding on top
+    brls_close(c);
+    return fail(nullptr, BRLS_EINVAL,
+                "wavefield storage of %lld floats is too large (limit %lld)",
+                (long long)c->fs, (long long)lim);
+  }
+  c->seg = round_up((int)((int64_t)g.nt_max * g.nrec_max), 64);
 
   int rc = BRLS_OK;
 #define ALLOC(ptr, n)                               \

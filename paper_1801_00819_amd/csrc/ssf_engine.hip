@@ -345,6 +345,9 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
     return sfail(nullptr, BRLS_EINVAL, "no DFT frequency in [%g, %g] Hz",
                  g.fmin, g.fmax);
   const int64_t M = (int64_t)g.nz * g.nx;
+  if (M >= ((int64_t)1 << 30) || (int64_t)g.nt * g.nrec_max > ((int64_t)1 << 30))
+    return sfail(nullptr, BRLS_EINVAL,
+                 "nz * nx and nt * nrec_max must stay below 2^30");
   for (int64_t i = 0; i < M; ++i)
     if (!(vel[i] > 0.f) || !std::isfinite(vel[i]))
       return sfail(nullptr, BRLS_EINVAL, "velocity must be positive and finite");

@@ -22,9 +22,11 @@ from . import _ptr
 class SsfContext:
     """One velocity model, one window of shots, one image."""
 
-    def __init__(self, handle, nz, nx, device):
+    def __init__(self, handle, nz, nx, nt, device):
         self._h = handle
         self.model_shape = (nz, nx)
+        self.model_size = nz * nx
+        self.nt = nt
         self.device = device
 
     def close(self):
@@ -60,7 +62,7 @@ class SsfContext:
         sh.rec = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         if data is not None and not self.device:
             data = np.ascontiguousarray(data, dtype=np.float32)
-        p = _ptr(data, self.device)
+        p = _ptr(data, self.device, self.nt * sh.nrec)
         sh.data = p.value if p is not None else None
         self._check(L.lib().brls_ssf_update(self._h, ctypes.byref(sh)))
 
@@ -115,7 +117,8 @@ class SsfContext:
         m = self._in(m)
         out = self._data_out(out)
         self._check(L.lib().brls_ssf_apply_born(
-            self._h, _ptr(m, self.device), _ptr(out, self.device)))
+            self._h, _ptr(m, self.device, self.model_size),
+            _ptr(out, self.device, self.window_data_size())))
         return out
 
     apply_born = brls_ssf_apply_born
@@ -124,15 +127,16 @@ class SsfContext:
         d = self._in(d)
         out = self._model_out(out)
         self._check(L.lib().brls_ssf_apply_adjoint(
-            self._h, _ptr(d, self.device), _ptr(out, self.device)))
+            self._h, _ptr(d, self.device, self.window_data_size()),
+            _ptr(out, self.device, self.model_size)))
         return out
 
     apply_adjoint = brls_ssf_apply_adjoint
 
     def brls_ssf_observed(self, out=None):
         out = self._data_out(out)
-        self._check(L.lib().brls_ssf_observed(self._h,
-                                              _ptr(out, self.device)))
+        self._check(L.lib().brls_ssf_observed(
+            self._h, _ptr(out, self.device, self.window_data_size())))
         return out
 
     observed = brls_ssf_observed
@@ -162,8 +166,8 @@ class SsfContext:
 
     def brls_ssf_illumination(self, out=None):
         out = self._model_out(out)
-        self._check(L.lib().brls_ssf_illumination(self._h,
-                                                  _ptr(out, self.device)))
+        self._check(L.lib().brls_ssf_illumination(
+            self._h, _ptr(out, self.device, self.model_size)))
         return out
 
     illumination = brls_ssf_illumination
@@ -185,15 +189,16 @@ class SsfContext:
 
     def brls_ssf_image(self, out=None):
         out = self._model_out(out)
-        self._check(L.lib().brls_ssf_image(self._h, _ptr(out, self.device)))
+        self._check(L.lib().brls_ssf_image(
+            self._h, _ptr(out, self.device, self.model_size)))
         return out
 
     image = brls_ssf_image
 
     def brls_ssf_set_image(self, m):
         m = self._in(m)
-        self._check(L.lib().brls_ssf_set_image(self._h,
-                                               _ptr(m, self.device)))
+        self._check(L.lib().brls_ssf_set_image(
+            self._h, _ptr(m, self.device, self.model_size)))
 
     set_image = brls_ssf_set_image
 
@@ -242,9 +247,12 @@ def brls_ssf_open(nz: int, nx: int, dx: float, dz: float, nt: int,
         import torch
         stream = torch.cuda.current_stream().cuda_stream
     v = np.ascontiguousarray(vel, dtype=np.float32)
+    if v.size < nz * nx:
+        raise ValueError(f"vel holds {v.size} values, the grid has "
+                         f"{nz * nx} points")
     h = ctypes.c_void_p()
     rc = L.lib().brls_ssf_open(ctypes.byref(g), v.ctypes.data,
                                ctypes.c_void_p(stream) if stream else None,
                                ctypes.byref(h))
     L.check_ssf(rc, None)
-    return SsfContext(h, nz, nx, device)
+    return SsfContext(h, nz, nx, nt, device)
