@@ -415,7 +415,8 @@ __global__ void k_adj_finalize3(const double* acc, int ngroups, Geo3D g,
 }
 
 static const TileShape3 kShapes3[] = {
-    {32, 8, 1}, {32, 8, 2}, {32, 8, 4}, {64, 4, 2}, {64, 4, 4}, {32, 4, 4},
+    {32, 8, 1}, {32, 8, 2}, {32, 8, 4}, {64, 4, 2},
+    {64, 4, 4}, {32, 4, 4}, {64, 8, 1}, {64, 8, 2},
 };
 constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 
@@ -467,6 +468,8 @@ hipError_t launch_step3d(int variant, int mode, const StepArgs& a,
     case 3: return launch3_shape<64, 4, 2>(mode, a, st);
     case 4: return launch3_shape<64, 4, 4>(mode, a, st);
     case 5: return launch3_shape<32, 4, 4>(mode, a, st);
+    case 6: return launch3_shape<64, 8, 1>(mode, a, st);
+    case 7: return launch3_shape<64, 8, 2>(mode, a, st);
   }
   return hipErrorInvalidValue;
 }

@@ -55,7 +55,7 @@ def _check(ctx, w, idx, m32, born, r, adj):
 
 
 @pytest.mark.parametrize("ckpt", [0, 9])
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(8))
 def test_every_3d_tile_matches_oracle(case, variant, ckpt):
     w, idx, m32, born, r, adj = case
     print(f"3-D variant {variant} ckpt={ckpt}", flush=True)
