@@ -216,6 +216,35 @@ def test_device_pointers_match_host(P):
     dctx.close()
 
 
+def test_device_buffers_are_checked_before_the_library(P):
+    """With device pointers the binding refuses a tensor smaller than the
+    call needs, or of another dtype, before any copy or kernel sees it;
+    the context stays usable."""
+    import torch
+    w, idx = _case("layers64")
+    ctx = open_ctx(w, q_max=2, device=True)
+    s = w.shots[idx[0]]
+    short = torch.zeros(s.nt * s.nrec - 1, dtype=torch.float32,
+                        device="cuda")
+    with pytest.raises(ValueError, match="needs"):
+        ctx.update(idx[0], s.src, s.rec, s.nt, s.f0, short)
+    ctx.update(idx[0], s.src, s.rec, s.nt, s.f0, None)
+    m = torch.from_numpy(f32(w.m_true)).cuda()
+    with pytest.raises(TypeError, match="float32"):
+        ctx.apply_born(m.double())
+    with pytest.raises(ValueError, match="needs"):
+        ctx.apply_born(m.ravel()[:-1].contiguous())
+    d = ctx.apply_born(m)
+    with pytest.raises(ValueError, match="needs"):
+        ctx.apply_adjoint(d[:-1].contiguous())
+    with pytest.raises(ValueError, match="needs"):
+        ctx.image(torch.empty(10, dtype=torch.float32, device="cuda"))
+    g = ctx.apply_adjoint(d)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g).all()
+    ctx.close()
+
+
 def test_runs_are_bitwise_repeatable(P):
     w, idx = _case("ragged2d")
     ctx = open_ctx(w, q_max=3)
