@@ -262,7 +262,8 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
          lam: float, niter: int, m0: Optional[np.ndarray] = None,
          rtol: float = 0.0, keep_iterates: bool = False,
          minv: Optional[np.ndarray] = None,
-         m_ref: Optional[np.ndarray] = None) -> CGLSResult:
+         m_ref: Optional[np.ndarray] = None,
+         weights: Optional[Sequence[float]] = None) -> CGLSResult:
     """CG on min ||A m - d||^2 + lam ||m||^2 (eq. 3 / eq. 10), least-squares
     form: one A and one A^T per iteration, all in FP64.
 
@@ -276,8 +277,16 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
     (the correction-regularised recursion when m_ref is the previous
     window's image).
 
+    With ``weights`` (one per shot of ``idx``, >= 0) shot j's misfit counts
+    w_j times: min sum_j w_j ||A_j m - d_j||^2 + lam ||m - m_ref||^2, CG on
+    (A^T W A + lam I) m = A^T W d with W the per-shot weights; the
+    exponentially weighted (forgetting-factor) window sets w_j = beta^age.
+    The search runs on the unweighted residual r = d - A m, with
+    s = A^T W r - lam (m - m_ref) and delta = <q, W q> + lam <p, p>.
+
     Stops after ``niter`` iterations, or earlier once
-    ||A^T r - lam m|| <= rtol * ||A^T d|| (s unpreconditioned in both)."""
+    ||A^T W r - lam m|| <= rtol * ||A^T W d|| (s unpreconditioned in
+    both)."""
     m = np.zeros(prob.grid.model_shape) if m0 is None else np.array(
         m0, dtype=np.float64).reshape(prob.grid.model_shape)
     d = [np.asarray(x, dtype=np.float64) for x in d]
@@ -285,16 +294,24 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
         minv, dtype=np.float64).reshape(prob.grid.model_shape)
     mr = np.zeros(prob.grid.model_shape) if m_ref is None else np.array(
         m_ref, dtype=np.float64).reshape(prob.grid.model_shape)
+    wts = np.ones(len(idx)) if weights is None else np.asarray(
+        weights, dtype=np.float64)
+    if wts.shape != (len(idx),) or not np.all(np.isfinite(wts)) or \
+            np.any(wts < 0):
+        raise ValueError("weights: one finite value >= 0 per shot")
+
+    def wt(x):  # W x, per shot
+        return [w * xi for w, xi in zip(wts, x)]
     Am = prob.born(m, idx)
     r = [di - ai for di, ai in zip(d, Am)]
-    s = prob.adjoint(r, idx) - lam * (m - mr)
+    s = prob.adjoint(wt(r), idx) - lam * (m - mr)
     z = s if w is None else w * s
     p = z.copy()
     gamma = float(np.vdot(s, z))
     snorm = float(np.linalg.norm(s))
     ref = None
     if rtol > 0:
-        ref = np.linalg.norm(prob.adjoint(d, idx))
+        ref = np.linalg.norm(prob.adjoint(wt(d), idx))
     res = CGLSResult(m, 0, snorm, [snorm], [np.sqrt(_dot(r, r))], [], [],
                      [m.copy()] if keep_iterates else None)
     for k in range(niter):
@@ -303,13 +320,13 @@ def cgls(prob: Problem, idx: Sequence[int], d: Sequence[np.ndarray],
         if gamma == 0.0:
             break
         q = prob.born(p, idx)
-        delta = _dot(q, q) + lam * float(np.vdot(p, p))
+        delta = _dot(q, wt(q)) + lam * float(np.vdot(p, p))
         if delta <= 0.0:
             raise ArithmeticError("CG breakdown: delta <= 0")
         alpha = gamma / delta
         m = m + alpha * p
         r = [ri - alpha * qi for ri, qi in zip(r, q)]
-        s = prob.adjoint(r, idx) - lam * (m - mr)
+        s = prob.adjoint(wt(r), idx) - lam * (m - mr)
         z = s if w is None else w * s
         gamma_new = float(np.vdot(s, z))
         beta = gamma_new / gamma
@@ -358,16 +375,25 @@ class ChainResult:
 
 def chain(prob: Problem, data: Sequence[np.ndarray], windows, lam: float,
           niter: int, m0: Optional[np.ndarray] = None,
-          correction: bool = False) -> ChainResult:
+          correction: bool = False,
+          forgetting: Optional[float] = None) -> ChainResult:
     """Block-row recursion (eqs. 10-11): solve each window's damped problem by
     CG, starting from the previous window's image (zero for the first).
     ``correction``: damp the correction to the previous image instead of the
-    image (min ||A_w m - d_w||^2 + lam ||m - m_{w-1}||^2)."""
+    image (min ||A_w m - d_w||^2 + lam ||m - m_{w-1}||^2). ``forgetting``:
+    a factor beta in (0, 1] weighting each shot's misfit by beta^age, age
+    the number of earlier windows that held it (the exponentially weighted
+    window of forgetting-factor RLS)."""
     m = m0
     images, results = [], []
-    for w in windows:
+    first = {}
+    for k, w in enumerate(windows):
+        for i in w:
+            first.setdefault(i, k)
+        wts = None if forgetting is None else \
+            [float(forgetting) ** (k - first[i]) for i in w]
         res = cgls(prob, w, [data[i] for i in w], lam, niter, m0=m,
-                   m_ref=m if correction else None)
+                   m_ref=m if correction else None, weights=wts)
         m = res.m
         images.append(m.copy())
         results.append(res)

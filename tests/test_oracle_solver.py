@@ -321,3 +321,73 @@ def test_correction_chain_keeps_memory(orc, dense_problem):
     assert np.linalg.norm(a.m.ravel() - np.linalg.solve(
         H, rhs + dp["lam"] * prev)) <= 1e-9 * np.linalg.norm(a.m)
     assert np.linalg.norm(a.m - b.m) > 1e-3 * np.linalg.norm(b.m)
+
+
+# --- per-shot weights: the exponentially weighted window ------------------
+
+def test_weighted_window_closed_form(orc, dense_problem):
+    """min sum_j w_j ||A_j m - d_j||^2 + lam ||m||^2 converges to
+    (A^T W A + lam I)^-1 A^T W d, W the per-shot weights spread over each
+    shot's samples (dense blocks)."""
+    dp = dense_problem
+    idx, wts = [0, 1, 2], [0.5, 2.0, 0.8]
+    A = np.concatenate([dp["blocks"][i] for i in idx], 0)
+    d = np.concatenate([dp["data"][i].ravel() for i in idx])
+    wv = np.concatenate([np.full(dp["blocks"][i].shape[0], w)
+                         for i, w in zip(idx, wts)])
+    H = A.T @ (wv[:, None] * A) + dp["lam"] * np.eye(dp["M"])
+    exact = np.linalg.solve(H, A.T @ (wv * d))
+    res = orc.cgls(dp["prob"], idx, [dp["data"][i] for i in idx], dp["lam"],
+                   150, weights=wts)
+    assert np.linalg.norm(res.m.ravel() - exact) <= 1e-9 * np.linalg.norm(
+        exact)
+
+
+def test_integer_weight_equals_a_repeated_shot(orc, dense_problem):
+    """Weight 2 on a shot gives the iterates of the window that holds the
+    shot twice."""
+    dp = dense_problem
+    d = dp["data"]
+    a = orc.cgls(dp["prob"], [0, 1], [d[0], d[1]], dp["lam"], 6,
+                 weights=[1.0, 2.0], keep_iterates=True)
+    b = orc.cgls(dp["prob"], [0, 1, 1], [d[0], d[1], d[1]], dp["lam"], 6,
+                 keep_iterates=True)
+    for xa, xb in zip(a.iterates, b.iterates):
+        assert np.linalg.norm(xa - xb) <= 1e-11 * max(np.linalg.norm(xb),
+                                                       1e-300)
+
+
+def test_zero_weight_drops_the_shot(orc, dense_problem):
+    dp = dense_problem
+    d = dp["data"]
+    a = orc.cgls(dp["prob"], [0, 1, 2], [d[0], d[1], d[2]], dp["lam"], 6,
+                 weights=[1.0, 0.0, 1.0])
+    b = orc.cgls(dp["prob"], [0, 2], [d[0], d[2]], dp["lam"], 6)
+    assert np.linalg.norm(a.m - b.m) <= 1e-12 * np.linalg.norm(b.m)
+
+
+def test_forgetting_chain_weights_shots_by_age(orc, dense_problem):
+    """Windows {0, 1} then {1, 2} with beta: in the second window shot 1
+    (held once before) weighs beta and shot 2 weighs 1; the chain's
+    windows are the weighted CG runs from the previous image."""
+    dp = dense_problem
+    wins, beta = [[0, 1], [1, 2]], 0.6
+    ch = orc.chain(dp["prob"], dp["data"], wins, dp["lam"], 5,
+                   forgetting=beta)
+    first = orc.cgls(dp["prob"], wins[0], [dp["data"][i] for i in wins[0]],
+                     dp["lam"], 5)
+    second = orc.cgls(dp["prob"], wins[1], [dp["data"][i] for i in wins[1]],
+                      dp["lam"], 5, m0=first.m, weights=[beta, 1.0])
+    assert np.array_equal(ch.images[0], first.m)
+    assert np.array_equal(ch.m, second.m)
+    plain = orc.chain(dp["prob"], dp["data"], wins, dp["lam"], 5)
+    assert np.linalg.norm(ch.m - plain.m) > 1e-3 * np.linalg.norm(plain.m)
+
+
+def test_weights_are_checked(orc, dense_problem):
+    dp = dense_problem
+    d = dp["data"]
+    for bad in ([1.0], [1.0, -1.0], [1.0, float("nan")]):
+        with pytest.raises(ValueError):
+            orc.cgls(dp["prob"], [0, 1], [d[0], d[1]], dp["lam"], 2,
+                     weights=bad)
