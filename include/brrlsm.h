@@ -189,6 +189,19 @@ int brls_get_precond(const brls_ctx* ctx, int32_t* mode);
 int brls_set_regularization(brls_ctx* ctx, int32_t mode);
 int brls_get_regularization(const brls_ctx* ctx, int32_t* mode);
 
+/* Misfit weight of one window shot (default 1, reset by brls_update): the
+ * window solve minimises sum_j w_j ||A_j m - d_j||^2 + the damping term,
+ * CG with A^T W r in place of A^T r and <q, W q> in place of ||q||^2 (the
+ * stop test then reads ||A^T W r - ...|| <= rtol ||A^T W d||). Setting
+ * w_j = beta^age at each slide, age the windows a shot has already been
+ * in, gives the exponentially weighted window of forgetting-factor RLS,
+ * the form of memory the paper's prior work uses (cited with eq. 11). The
+ * illumination preconditioner stays unweighted. Weight 0 leaves the shot
+ * in the window without effect. Errors: BRLS_ENOSHOT; BRLS_EINVAL for a
+ * negative or non-finite weight. */
+int brls_set_shot_weight(brls_ctx* ctx, int64_t id, double w);
+int brls_get_shot_weight(const brls_ctx* ctx, int64_t id, double* w);
+
 /* The window's illumination [nz][ny][nx]: at each model point the sum over
  * the window's shots and time levels n = 0 .. nt-2 of (D2 u0^n)^2, the
  * squared Born source of eq. 1's linearisation (F2). Needs stored Born

@@ -183,6 +183,21 @@ class Context:
 
     set_regularization = brls_set_regularization
 
+    def brls_set_shot_weight(self, id: int, w: float):
+        """Misfit weight of a window shot (1 by default; beta^age gives the
+        exponentially weighted window)."""
+        self._check(L.lib().brls_set_shot_weight(self._h, int(id), float(w)))
+
+    set_shot_weight = brls_set_shot_weight
+
+    def brls_get_shot_weight(self, id: int) -> float:
+        v = ctypes.c_double()
+        self._check(L.lib().brls_get_shot_weight(self._h, int(id),
+                                                 ctypes.byref(v)))
+        return v.value
+
+    get_shot_weight = brls_get_shot_weight
+
     def brls_get_regularization(self) -> int:
         v = ctypes.c_int32()
         self._check(L.lib().brls_get_regularization(self._h,

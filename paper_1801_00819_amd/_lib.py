@@ -103,6 +103,9 @@ SIGNATURES = [
     ("brls_set_image", _I32, [_VP, _VP]),
     ("brls_set_precond", _I32, [_VP, _I32]),
     ("brls_set_regularization", _I32, [_VP, _I32]),
+    ("brls_set_shot_weight", _I32, [_VP, ctypes.c_int64, ctypes.c_double]),
+    ("brls_get_shot_weight", _I32,
+     [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     ("brls_get_regularization", _I32, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_get_precond", _I32, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_illumination", _I32, [_VP, _VP]),

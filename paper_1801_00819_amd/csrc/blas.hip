@@ -114,6 +114,13 @@ __global__ void k_mul(float* z, const float* a, const float* b, int64_t n) {
     z[i] = a[i] * b[i];
 }
 
+__global__ void k_scale_segments(float* y, const float* x, const float* w,
+                                 int64_t seg, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = w[i / seg] * x[i];
+}
+
 __global__ void k_recip_shift(float* y, const float* x, double shift,
                               int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -204,6 +211,14 @@ hipError_t launch_mul(float* z, const float* a, const float* b, int64_t n,
                       hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(256), 0, st, z, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_segments(float* y, const float* x, const float* w,
+                                 int64_t seg, int64_t n, hipStream_t st) {
+  if (n <= 0 || seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_segments, dim3(grid_for(n)), dim3(256), 0, st, y,
+                     x, w, seg, n);
   return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct Slot {
   int2* rent = nullptr;      // [nrec_max]
   int* rsidx = nullptr;      // [nrec_max]
   int64_t dat_off = 0;
+  float weight = 1.f;        // the shot's misfit weight in the window CG
 };
 
 struct Timer {
@@ -116,6 +117,8 @@ struct brls_ctx {
   float* dm = nullptr;    // that correction (mode 1)
   double* acc = nullptr;
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr;
+  float* wslot = nullptr;  // [q_max] per-slot misfit weights (device)
+  std::vector<float> wslot_h;  // their host copy, uploaded by the solve
   double *partial = nullptr, *scal = nullptr;
   int* flag = nullptr;
   ShotDev* tab_dev = nullptr;
@@ -866,6 +869,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   ALLOC(c->r, (int64_t)g.q_max * c->seg);
   ALLOC(c->q, (int64_t)g.q_max * c->seg);
   ALLOC(c->dscr, (int64_t)g.q_max * c->seg);
+  ALLOC(c->wslot, g.q_max);
   ALLOC(c->partial, kDotBlocks);
   ALLOC(c->scal, 16);
   ALLOC(c->flag, 1);
@@ -1020,6 +1024,7 @@ int brls_update(brls_ctx* c, const brls_shot* sh) {
   int rc = build_receiver_tiles(c, sl);  // synchronises
   if (rc) return rc;
   sl.used = true;
+  sl.weight = 1.f;
   sl.bg_ready = false;
   sl.seq = c->next_seq++;
   rebuild_order(c);
@@ -1091,6 +1096,25 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
   const int64_t M = c->mplane, D = (int64_t)c->g.q_max * c->seg;
   double sc[2];
   int rc;
+  // per-shot misfit weights W (all 1 unless set): the adjoint takes W r
+  // (written into the adjoint's input buffer) and delta = <q, W q> + ...
+  c->wslot_h.assign(c->g.q_max, 1.f);
+  bool weighted = false;
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (c->slots[i].used) {
+      c->wslot_h[i] = c->slots[i].weight;
+      weighted |= c->slots[i].weight != 1.f;
+    }
+  if (weighted)
+    HIPCHECK(c, hipMemcpyAsync(c->wslot, c->wslot_h.data(),
+                               (size_t)c->g.q_max * 4, hipMemcpyHostToDevice,
+                               c->st));
+  // adjoint of W x (x itself when unweighted)
+  auto adjoint_w = [&](const float* x) -> int {
+    if (!weighted) return adjoint_of(c, x);
+    HIPCHECK(c, launch_scale_segments(c->dscr, x, c->wslot, c->seg, D, c->st));
+    return adjoint_of(c, c->dscr);
+  };
   // r = d - A m
   if ((rc = born_of(c, c->m))) return finish(rc);
   HIPCHECK(c, launch_sub(c->r, c->dobs, c->q, D, c->st));
@@ -1099,7 +1123,7 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
   const bool corr = c->regularize == 1;
   if (corr) HIPCHECK(c, launch_fill_f32(c->dm, M, 0.f, c->st));
   const float* damped = corr ? c->dm : c->m;
-  if ((rc = adjoint_of(c, c->r))) return finish(rc);
+  if ((rc = adjoint_w(c->r))) return finish(rc);
   HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                                c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
@@ -1110,7 +1134,7 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
   st.s_norm = st.s0_norm;
   double ref = 0.0;
   if (rtol > 0) {
-    if ((rc = adjoint_of(c, c->dobs))) return finish(rc);
+    if ((rc = adjoint_w(c->dobs))) return finish(rc);
     HIPCHECK(c, launch_dot(c->gbuf, c->gbuf, M, c->partial, c->scal, c->st));
     if ((rc = read_scalars(c, sc, 1))) return finish(rc);
     ref = std::sqrt(sc[0]);
@@ -1133,7 +1157,11 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
     if (gamma == 0.0) break;
     if (rtol > 0 && snorm <= rtol * ref) break;
     if ((rc = born_of(c, c->p))) return finish(rc);
-    HIPCHECK(c, launch_dot(c->q, c->q, D, c->partial, c->scal, c->st));
+    if (weighted)
+      HIPCHECK(c, launch_scale_segments(c->dscr, c->q, c->wslot, c->seg, D,
+                                        c->st));
+    HIPCHECK(c, launch_dot(c->q, weighted ? c->dscr : c->q, D, c->partial,
+                           c->scal, c->st));
     HIPCHECK(c, launch_dot(c->p, c->p, M, c->partial, c->scal + 1, c->st));
     if ((rc = read_scalars(c, sc, 2))) return finish(rc);
     const double delta = sc[0] + lam * sc[1];
@@ -1146,7 +1174,7 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
     HIPCHECK(c, launch_axpy(c->m, c->p, alpha, M, c->st));
     if (corr) HIPCHECK(c, launch_axpy(c->dm, c->p, alpha, M, c->st));
     HIPCHECK(c, launch_axpy(c->r, c->q, -alpha, D, c->st));
-    if ((rc = adjoint_of(c, c->r))) return finish(rc);
+    if ((rc = adjoint_w(c->r))) return finish(rc);
     HIPCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                                  c->scal, c->st));
     if (pre) {
@@ -1168,6 +1196,25 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
   st.r_norm = std::sqrt(sc[0]);
   return finish(BRLS_OK);
+}
+
+int brls_set_shot_weight(brls_ctx* c, int64_t id, double w) {
+  if (!c) return BRLS_EINVAL;
+  const int i = find_slot(c, id);
+  if (i < 0)
+    return fail(c, BRLS_ENOSHOT, "no shot %lld in the window", (long long)id);
+  if (!(w >= 0.0) || !std::isfinite(w))
+    return fail(c, BRLS_EINVAL, "shot weight %g: must be finite and >= 0", w);
+  c->slots[i].weight = (float)w;
+  return BRLS_OK;
+}
+
+int brls_get_shot_weight(const brls_ctx* c, int64_t id, double* w) {
+  if (!c || !w) return BRLS_EINVAL;
+  const int i = find_slot(c, id);
+  if (i < 0) return BRLS_ENOSHOT;
+  *w = c->slots[i].weight;
+  return BRLS_OK;
 }
 
 int brls_image(brls_ctx* c, float* out) {

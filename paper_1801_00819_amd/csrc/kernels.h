@@ -85,6 +85,10 @@ hipError_t launch_sumsq_frames(const float* x, int64_t nframes, int64_t n,
 // z = a * b elementwise
 hipError_t launch_mul(float* z, const float* a, const float* b, int64_t n,
                       hipStream_t st);
+// y[i] = w[i / seg] * x[i]: one weight per data segment of seg floats
+// (n a multiple of seg; y may alias x)
+hipError_t launch_scale_segments(float* y, const float* x, const float* w,
+                                 int64_t seg, int64_t n, hipStream_t st);
 // y = 1 / (x + shift) (float64 arithmetic; y may alias x)
 hipError_t launch_recip_shift(float* y, const float* x, double shift,
                               int64_t n, hipStream_t st);

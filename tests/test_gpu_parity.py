@@ -271,9 +271,9 @@ def _chain_inputs(w, noise_seed_cfg):
     return prob, data, lam
 
 
-def _gpu_chain(ctx, w, data, niter):
-    held = []
-    for win in w.windows():
+def _gpu_chain(ctx, w, data, niter, forgetting=None):
+    held, first = [], {}
+    for k, win in enumerate(w.windows()):
         for i in list(held):
             if i not in win:
                 ctx.downdate(i)
@@ -282,6 +282,9 @@ def _gpu_chain(ctx, w, data, niter):
             if i not in held:
                 add_shot(ctx, w, i, data[i])
                 held.append(i)
+            first.setdefault(i, k)
+            if forgetting is not None:
+                ctx.set_shot_weight(i, forgetting ** (k - first[i]))
         st = ctx.solve_window(niter)
         assert st["iters"] == niter
     return ctx.image()
@@ -594,6 +597,79 @@ def test_correction_regularised_chain_matches_oracle(P, mode):
     ctx.close()
     assert rel(img, ref.m) <= IMG_TOL
     assert rel(img, plain.m) > 10 * IMG_TOL
+
+
+@pytest.mark.parametrize("mode,correction", [(0, False), (2, True)])
+def test_forgetting_factor_chain_matches_oracle(P, mode, correction):
+    """The 64 x 64 chain with each shot's misfit weighted by beta^age
+    (exponentially weighted window), alone and with the correction-
+    regularised damping, vs the oracle's chain with the same factor.
+    beta = 0.8, in the range forgetting factors take: at 0.5 the three
+    truncated 10-iteration solves amplify float32 rounding to 1.2e-4 (the
+    unweighted chain: 1.4e-5, beta = 0.8: 1.8e-6)."""
+    import oracle
+    w = synth.layers2d_64x64()
+    prob, data, lam = _chain_inputs(w, 0)
+    d64 = [d.astype(np.float64) for d in data]
+    beta = 0.8
+    ref = oracle.chain(prob, d64, w.windows(), lam, w.niter,
+                       correction=correction, forgetting=beta)
+    plain = oracle.chain(prob, d64, w.windows(), lam, w.niter,
+                         correction=correction)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    ctx.set_tuning(*_bench_tuning())
+    ctx.set_exec(mode)
+    ctx.set_regularization(int(correction))
+    img = _gpu_chain(ctx, w, data, w.niter, forgetting=beta)
+    ctx.close()
+    print(f"forgetting chain rel {rel(img, ref.m):.2e}")
+    assert rel(img, ref.m) <= IMG_TOL
+    assert rel(img, plain.m) > 10 * IMG_TOL
+
+
+def test_shot_weights_window_and_errors(P):
+    """Weights (0.5, 2) on a two-shot window vs the oracle's weighted CG;
+    weight 0 gives the library's own solve of the window without the shot
+    (exactly: the zero-weighted shot adds zeros to every sum; the oracle
+    pins weight 0 to dropping the shot); the weight resets to 1 when a
+    shot is added again; bad ids and weights are refused."""
+    import oracle
+    w = synth.layers2d_64x64()
+    prob, data, lam = _chain_inputs(w, 0)
+    idx = w.windows()[0]
+    d64 = [data[i].astype(np.float64) for i in idx]
+    ref = oracle.cgls(prob, idx, d64, lam, w.niter, weights=[0.5, 2.0])
+    one = open_ctx(w, lam=lam, q_max=w.Q)
+    one.set_tuning(*_bench_tuning())
+    add_shot(one, w, idx[0], data[idx[0]])
+    one.solve_window(w.niter)
+    drop = one.image()
+    one.close()
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    ctx.set_tuning(*_bench_tuning())
+    for i in idx:
+        add_shot(ctx, w, i, data[i])
+        assert ctx.get_shot_weight(i) == 1.0
+    ctx.set_shot_weight(idx[0], 0.5)
+    ctx.set_shot_weight(idx[1], 2.0)
+    ctx.solve_window(w.niter)
+    assert rel(ctx.image(), ref.m) <= IMG_TOL
+    ctx.set_image(np.zeros(w.model_shape, np.float32))
+    ctx.set_shot_weight(idx[0], 1.0)
+    ctx.set_shot_weight(idx[1], 0.0)
+    ctx.solve_window(w.niter)
+    assert rel(ctx.image(), drop) <= 1e-7
+    ctx.downdate(idx[1])
+    add_shot(ctx, w, idx[1], data[idx[1]])
+    assert ctx.get_shot_weight(idx[1]) == 1.0
+    with pytest.raises(P.BrlsError) as e:
+        ctx.set_shot_weight(999, 1.0)
+    assert e.value.code == -4
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(P.BrlsError) as e:
+            ctx.set_shot_weight(idx[0], bad)
+        assert e.value.code == -1
+    ctx.close()
 
 
 @pytest.mark.parametrize("cfg", ["two-step", "staged", "marching", "ckpt"])
