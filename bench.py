@@ -107,6 +107,9 @@ def parse():
                     help="stream workload: shots taken from the 512")
     ap.add_argument("--stream-iters", type=int, default=5,
                     help="stream workload: CG iterations per window")
+    ap.add_argument("--stream-forgetting", type=float, default=0.8,
+                    help="stream workload: forgetting factor of the "
+                         "weighted-window run (shot weights beta^age)")
     ap.add_argument("--stream-plain-windows", type=int, default=4,
                     help="stream workload: windows run with plain launches")
     ap.add_argument("--fr-windows", type=int, default=3,
@@ -559,7 +562,7 @@ def bench_stream(args, P, synth, torch):
         x += 0.01 * rms * torch.randn(x.shape, generator=gen, device="cuda")
     log(f"stream: data for {nsh} shots in {time.perf_counter() - t0:.1f}s")
 
-    def run(Q, exec_mode, nwin, regularize=0):
+    def run(Q, exec_mode, nwin, regularize=0, forgetting=None):
         w = synth.stream2d_512x1024(nshots=nsh, Q=Q)
         wins = w.windows()[:nwin]
         c = P.brls_open(2, w.nz, 1, w.nx, w.nb, nt_max, nrec_max, Q, w.h,
@@ -589,7 +592,8 @@ def bench_stream(args, P, synth, torch):
         m0 = torch.from_numpy(w.m_true).cuda()
         drift = torch.from_numpy(w.extra["drift"]).cuda()
         held, lat, its, err, chg = [], [], [], [], []
-        for win in wins:
+        first = {}
+        for k, win in enumerate(wins):
             torch.cuda.synchronize()
             t = time.perf_counter()
             for i in list(held):
@@ -601,6 +605,9 @@ def bench_stream(args, P, synth, torch):
                     s = w.shots[i]
                     c.update(i, s.src, s.rec, s.nt, s.f0, data[i])
                     held.append(i)
+                first.setdefault(i, k)
+                if forgetting is not None:  # exponentially weighted window
+                    c.set_shot_weight(i, forgetting ** (k - first[i]))
             st = c.solve_window(args.stream_iters)
             c.image(image)
             torch.cuda.synchronize()
@@ -651,6 +658,12 @@ def bench_stream(args, P, synth, torch):
     lat, _, err, chg = run(8, P.BRLS_EXEC_GRAPH, 10 ** 9, regularize=1)
     corr = summary(lat, err, chg)
     log(f"stream Q=8 correction-regularised: {corr}")
+    # and with each shot's misfit weighted by beta^age (forgetting factor)
+    lat, _, err, chg = run(8, P.BRLS_EXEC_GRAPH, 10 ** 9, regularize=1,
+                           forgetting=args.stream_forgetting)
+    forget = summary(lat, err, chg)
+    forget["beta"] = args.stream_forgetting
+    log(f"stream Q=8 correction-regularised, weighted window: {forget}")
     out = {
         "metric": "window solve latency p50 (Q=8)",
         "value": per_q[8]["p50_s"],
@@ -666,6 +679,7 @@ def bench_stream(args, P, synth, torch):
                                "shots"},
         "per_window_size": {str(k): v for k, v in per_q.items()},
         "correction_regularised_q8": corr,
+        "correction_regularised_weighted_q8": forget,
     }
     print(json.dumps(out), flush=True)
 
