@@ -151,6 +151,14 @@ int brls_ssf_illumination(brls_ssf_ctx* ctx, float* out);
 int brls_ssf_set_regularization(brls_ssf_ctx* ctx, int32_t mode);
 int brls_ssf_get_regularization(const brls_ssf_ctx* ctx, int32_t* mode);
 
+/* Misfit weight of one window shot (default 1, reset by brls_ssf_update),
+ * as brls_set_shot_weight: the solve minimises
+ * sum_j w_j ||A_j m - d_j||^2 + the damping term; w_j = beta^age gives the
+ * exponentially weighted (forgetting-factor) window. Errors: BRLS_ENOSHOT;
+ * BRLS_EINVAL for a negative or non-finite weight. */
+int brls_ssf_set_shot_weight(brls_ssf_ctx* ctx, int64_t id, double w);
+int brls_ssf_get_shot_weight(const brls_ssf_ctx* ctx, int64_t id, double* w);
+
 /* Copy the current image out / set it (the next solve starts there). */
 int brls_ssf_image(brls_ssf_ctx* ctx, float* out);
 int brls_ssf_set_image(brls_ssf_ctx* ctx, const float* m);

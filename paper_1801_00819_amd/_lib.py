@@ -155,6 +155,9 @@ SIGNATURES = [
     ("brls_ssf_get_precond", _I32, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_ssf_illumination", _I32, [_VP, _VP]),
     ("brls_ssf_set_regularization", _I32, [_VP, _I32]),
+    ("brls_ssf_set_shot_weight", _I32, [_VP, ctypes.c_int64, ctypes.c_double]),
+    ("brls_ssf_get_shot_weight", _I32,
+     [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     ("brls_ssf_get_regularization", _I32,
      [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_ssf_image", _I32, [_VP, _VP]),

@@ -40,6 +40,7 @@ struct SsfSlot {
   int64_t id = 0;
   int xs = 0, nrec = 0;
   double f0 = 0.0;
+  float weight = 1.f;  // the shot's misfit weight in the window CG
 };
 
 }  // namespace
@@ -77,6 +78,8 @@ struct brls_ssf_ctx {
   int precond = 0;     // 1: diagonal illumination preconditioner
   int regularize = 0;  // 1: damp the correction to the starting image
   float *minv = nullptr, *z = nullptr, *dm = nullptr;
+  float* wslot = nullptr;      // [q_max] per-slot misfit weights (device)
+  std::vector<float> wslot_h;  // their host copy, uploaded by the solve
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr,
         *dtime = nullptr;
   double *partial = nullptr, *scal = nullptr;
@@ -426,6 +429,7 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
       (rc = salloc(c, &c->dm, M)) ||
       (rc = salloc(c, &c->dobs, D)) || (rc = salloc(c, &c->r, D)) ||
       (rc = salloc(c, &c->q, D)) || (rc = salloc(c, &c->dscr, D)) ||
+      (rc = salloc(c, &c->wslot, (int64_t)g.q_max)) ||
       (rc = salloc(c, &c->dtime, (int64_t)g.nt * g.nrec_max)) ||
       (rc = salloc(c, &c->partial, kDotBlocks)) ||
       (rc = salloc(c, &c->scal, 4)) || (rc = salloc(c, &c->flag, 1)) ||
@@ -601,6 +605,7 @@ int brls_ssf_update(brls_ssf_ctx* c, const brls_ssf_shot* sh) {
   SCHECK(c, hipStreamSynchronize(c->st));
   SsfSlot& sl = c->slots[sidx];
   sl.used = true;
+  sl.weight = 1.f;
   sl.w_ready = false;
   sl.id = sh->id;
   sl.xs = sh->xs;
@@ -685,9 +690,27 @@ int brls_ssf_solve_window(brls_ssf_ctx* c, int32_t max_iter, double rtol,
   const bool corr = c->regularize == 1;
   if (corr) SCHECK(c, launch_fill_f32(c->dm, M, 0.f, c->st));
   const float* damped = corr ? c->dm : c->m;
+  // per-shot misfit weights W (all 1 unless set): the adjoint takes W r and
+  // delta = <q, W q> + ...
+  c->wslot_h.assign(c->g.q_max, 1.f);
+  bool weighted = false;
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (c->slots[i].used) {
+      c->wslot_h[i] = c->slots[i].weight;
+      weighted |= c->slots[i].weight != 1.f;
+    }
+  if (weighted)
+    SCHECK(c, hipMemcpyAsync(c->wslot, c->wslot_h.data(),
+                             (size_t)c->g.q_max * 4, hipMemcpyHostToDevice,
+                             c->st));
+  auto adjoint_w = [&](const float* x) -> int {
+    if (!weighted) return adjoint_of(c, x);
+    SCHECK(c, launch_scale_segments(c->dscr, x, c->wslot, c->seg, D, c->st));
+    return adjoint_of(c, c->dscr);
+  };
   if ((rc = born_of(c, c->m))) return finish(rc);
   SCHECK(c, launch_sub(c->r, c->dobs, c->q, D, c->st));
-  if ((rc = adjoint_of(c, c->r))) return finish(rc);
+  if ((rc = adjoint_w(c->r))) return finish(rc);
   SCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                              c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
@@ -698,7 +721,7 @@ int brls_ssf_solve_window(brls_ssf_ctx* c, int32_t max_iter, double rtol,
   double snorm = st.s0_norm;
   double ref = 0.0;
   if (rtol > 0) {
-    if ((rc = adjoint_of(c, c->dobs))) return finish(rc);
+    if ((rc = adjoint_w(c->dobs))) return finish(rc);
     SCHECK(c, launch_dot(c->gbuf, c->gbuf, M, c->partial, c->scal, c->st));
     if ((rc = read_scalars(c, sc, 1))) return finish(rc);
     ref = std::sqrt(sc[0]);
@@ -720,7 +743,11 @@ int brls_ssf_solve_window(brls_ssf_ctx* c, int32_t max_iter, double rtol,
     if (gamma == 0.0) break;
     if (rtol > 0 && snorm <= rtol * ref) break;
     if ((rc = born_of(c, c->p))) return finish(rc);
-    SCHECK(c, launch_dot(c->q, c->q, D, c->partial, c->scal, c->st));
+    if (weighted)
+      SCHECK(c, launch_scale_segments(c->dscr, c->q, c->wslot, c->seg, D,
+                                      c->st));
+    SCHECK(c, launch_dot(c->q, weighted ? c->dscr : c->q, D, c->partial,
+                         c->scal, c->st));
     SCHECK(c, launch_dot(c->p, c->p, M, c->partial, c->scal + 1, c->st));
     if ((rc = read_scalars(c, sc, 2))) return finish(rc);
     const double delta = sc[0] + lam * sc[1];
@@ -733,7 +760,7 @@ int brls_ssf_solve_window(brls_ssf_ctx* c, int32_t max_iter, double rtol,
     SCHECK(c, launch_axpy(c->m, c->p, alpha, M, c->st));
     if (corr) SCHECK(c, launch_axpy(c->dm, c->p, alpha, M, c->st));
     SCHECK(c, launch_axpy(c->r, c->q, -alpha, D, c->st));
-    if ((rc = adjoint_of(c, c->r))) return finish(rc);
+    if ((rc = adjoint_w(c->r))) return finish(rc);
     SCHECK(c, launch_grad_norm(c->s, c->gbuf, damped, lam, M, c->partial,
                                c->scal, c->st));
     if (pre) {
@@ -782,6 +809,27 @@ int brls_ssf_set_regularization(brls_ssf_ctx* c, int32_t mode) {
 int brls_ssf_get_regularization(const brls_ssf_ctx* c, int32_t* mode) {
   if (!c || !mode) return BRLS_EINVAL;
   *mode = c->regularize;
+  return BRLS_OK;
+}
+
+int brls_ssf_set_shot_weight(brls_ssf_ctx* c, int64_t id, double w) {
+  if (!c) return BRLS_EINVAL;
+  const int i = find_slot(c, id);
+  if (i < 0)
+    return sfail(c, BRLS_ENOSHOT, "no shot %lld in the window",
+                 (long long)id);
+  if (!(w >= 0.0) || !std::isfinite(w))
+    return sfail(c, BRLS_EINVAL, "shot weight %g: must be finite and >= 0",
+                 w);
+  c->slots[i].weight = (float)w;
+  return BRLS_OK;
+}
+
+int brls_ssf_get_shot_weight(const brls_ssf_ctx* c, int64_t id, double* w) {
+  if (!c || !w) return BRLS_EINVAL;
+  const int i = find_slot(c, id);
+  if (i < 0) return BRLS_ENOSHOT;
+  *w = c->slots[i].weight;
   return BRLS_OK;
 }
 

@@ -187,6 +187,21 @@ class SsfContext:
 
     get_regularization = brls_ssf_get_regularization
 
+    def brls_ssf_set_shot_weight(self, id: int, w: float):
+        """Misfit weight of a window shot (1 by default)."""
+        self._check(L.lib().brls_ssf_set_shot_weight(self._h, int(id),
+                                                     float(w)))
+
+    set_shot_weight = brls_ssf_set_shot_weight
+
+    def brls_ssf_get_shot_weight(self, id: int) -> float:
+        v = ctypes.c_double()
+        self._check(L.lib().brls_ssf_get_shot_weight(self._h, int(id),
+                                                     ctypes.byref(v)))
+        return v.value
+
+    get_shot_weight = brls_ssf_get_shot_weight
+
     def brls_ssf_image(self, out=None):
         out = self._model_out(out)
         self._check(L.lib().brls_ssf_image(

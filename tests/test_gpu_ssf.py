@@ -225,6 +225,53 @@ def test_solver_options_match_oracle(P, precond, regularize):
     ctx.close()
 
 
+@pytest.mark.parametrize("correction", [False, True])
+def test_forgetting_factor_chain_matches_oracle(P, correction):
+    """Windows {0, 1} then {1, 2} with each shot's misfit weighted by
+    0.8^age (exponentially weighted window), alone and with the
+    correction-regularised damping, vs the oracle's chain; bad weights and
+    ids are refused."""
+    import oracle
+    w = synth.ssf_small()
+    prob = _oracle(w)
+    xt = [_time_data(w, i, 840 + i) for i in range(3)]
+    data = [prob.observed(x.astype(np.float64)) for x in xt]
+    lam = w.lam_rel * oracle.power_norm(prob, w.windows()[0], 20, seed=3)
+    beta = 0.8
+    ref = oracle.chain(prob, data, w.windows(), lam, w.niter,
+                       correction=correction, forgetting=beta)
+    plain = oracle.chain(prob, data, w.windows(), lam, w.niter,
+                         correction=correction)
+    ctx = _open(w, q_max=2, lam=lam)
+    ctx.set_regularization(int(correction))
+    held, first = [], {}
+    for k, win in enumerate(w.windows()):
+        for i in list(held):
+            if i not in win:
+                ctx.downdate(i)
+                held.remove(i)
+        for i in win:
+            if i not in held:
+                s = w.shots[i]
+                ctx.update(i, s.xs, s.rec, s.f0, xt[i])
+                held.append(i)
+                assert ctx.get_shot_weight(i) == 1.0
+            first.setdefault(i, k)
+            ctx.set_shot_weight(i, beta ** (k - first[i]))
+        ctx.solve_window(w.niter)
+    img = ctx.image()
+    print(f"forgetting chain rel {rel(img, ref.m):.2e}")
+    assert rel(img, ref.m) <= IMG_TOL
+    assert rel(img, plain.m) > 10 * IMG_TOL
+    with pytest.raises(P.BrlsError) as e:
+        ctx.set_shot_weight(99, 1.0)
+    assert e.value.code == -4
+    with pytest.raises(P.BrlsError) as e:
+        ctx.set_shot_weight(held[0], -0.5)
+    assert e.value.code == -1
+    ctx.close()
+
+
 def test_errors(P):
     w = synth.ssf_small()
     ctx = _open(w, q_max=2)
