@@ -66,9 +66,9 @@ TRAFFIC_2D = {
 # WRITE_SIZE x 1.000, the factors a 512 MiB device copy reads in the same
 # program), valid for the kernel sources of that hash.
 TRAFFIC_SSF = {
-    "sources_sha256_16": "4b5947b7cad94a2a",
-    "born": 2 * 1187398.6 * 1024 + 566.2 * 1024,
-    "adjoint": 2 * 1496217.3 * 1024 + 773120.0 * 1024,
+    "sources_sha256_16": "9b68de91c98c97be",
+    "born": 2 * 1133856.9 * 1024 + 566.2 * 1024,
+    "adjoint": 2 * 1538643.5 * 1024 + 773120.0 * 1024,
 }
 
 

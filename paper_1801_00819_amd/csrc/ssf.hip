@@ -360,11 +360,11 @@ __device__ void step_down(March<L, T>& s, const SsfArgs& a, const Level& lv,
 // One block per (pending shot, frequency).
 template <int L>
 __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_source(
-    SsfArgs a, const SsfShotDev* __restrict__ pend) {
+    SsfArgs a, const SsfShotDev* __restrict__ pend, int npend) {
   constexpr int N = Geo<L>::N, Q = Geo<L>::Q;
   __shared__ double2 b0[N], b1[N];
-  const int pi = blockIdx.x / a.nw;
-  const int k = blockIdx.x - pi * a.nw;
+  int pi, k;
+  if (!item_of(blockIdx.x, npend, a.nw, &pi, &k)) return;
   const int slot = pend[pi].slot, xs = pend[pi].xs;
   March<L, double> s;
   march_init<L, double>(s, a, k, a.tw64);
@@ -390,7 +390,23 @@ __global__ __launch_bounds__(Geo<L>::kBlock) void k_ssf_source(
     if (j + 1 < a.nz) {
       Level nxt;
       load_level<L>(nxt, a, j + 1, s.tx);
-      step_down<L, double>(s, a, cur, v, b0, b1);
+      // level j's factors from the double tables (the values step_down
+      // would evaluate), loaded before the forward FFT
+      const int64_t row = ((int64_t)k * a.nz + j) * N;
+      double2 pk[4], sx[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pk[r] = a.ptab64[row + s.tx + r * Q];
+        sx[r] = a.sstab64[row + s.tx + r * Q];
+      }
+      fft<L, double2>(v, b0, b1, s.tw, s.t, s.pb);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        v[r] = cscale(cmul(v[r], pk[r]), 1.0 / N);
+      ifft<L, double2>(v, b0, b1, s.tw, s.t, s.pb);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        v[r] = cscale(cmul(v[r], sx[r]), s.tau[r]);
       cur = nxt;
     }
   }
@@ -537,7 +553,9 @@ __global__ __launch_bounds__(256) void k_ssf_illumination(SsfArgs a,
 // formed from its angle in double and rounded once to float.
 __global__ __launch_bounds__(256) void k_ssf_tables(SsfArgs a, int n,
                                                     float2* ptab,
-                                                    float2* sstab) {
+                                                    float2* sstab,
+                                                    double2* ptab64,
+                                                    double2* sstab64) {
   const int64_t total = (int64_t)a.nw * a.nz * n;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -552,6 +570,8 @@ __global__ __launch_bounds__(256) void k_ssf_tables(SsfArgs a, int n,
                      1.0f / n);
     sstab[e] = cscale(cis<float>(-w * a.theta[(int64_t)j * n + q]),
                       a.tau[q]);
+    ptab64[e] = kz_phase<double>(w * a.s0[j], kx * kx, a.dz);
+    sstab64[e] = cis<double>(-w * a.theta[(int64_t)j * n + q]);
   }
 }
 
@@ -660,8 +680,10 @@ hipError_t launch_ssf_source(const SsfArgs& a, const SsfShotDev* pend,
                              int npend, hipStream_t st) {
   if (a.nw <= 0 || npend <= 0) return hipSuccess;
   SSF_DISPATCH(a.log2n,
-               hipLaunchKernelGGL(k_ssf_source<L>, dim3(a.nw * npend),
-                                  dim3(Geo<L>::kBlock), 0, st, a, pend));
+               hipLaunchKernelGGL(k_ssf_source<L>,
+                                  dim3(item_blocks(npend, a.nw)),
+                                  dim3(Geo<L>::kBlock), 0, st, a, pend,
+                                  npend));
   return hipGetLastError();
 }
 
@@ -688,13 +710,14 @@ hipError_t launch_ssf_adjoint(const SsfArgs& a, const float* d, float* part,
 }
 
 hipError_t launch_ssf_tables(const SsfArgs& a, float2* ptab, float2* sstab,
+                             double2* ptab64, double2* sstab64,
                              hipStream_t st) {
   const int n = 1 << a.log2n;
   const int64_t total = (int64_t)a.nw * a.nz * n;
   if (total <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 16);
   hipLaunchKernelGGL(k_ssf_tables, dim3((unsigned)blocks), dim3(256), 0, st,
-                     a, n, ptab, sstab);
+                     a, n, ptab, sstab, ptab64, sstab64);
   return hipGetLastError();
 }
 

@@ -67,6 +67,7 @@ struct brls_ssf_ctx {
   float2* W = nullptr;
   double2* wav = nullptr;
   float2 *ptab = nullptr, *sstab = nullptr;  // phase tables
+  double2 *ptab64 = nullptr, *sstab64 = nullptr;  // the same in double
   int *rec = nullptr, *colptr = nullptr, *cidx = nullptr;
   SsfShotDev* tab = nullptr;
   SsfShotDev* pend = nullptr;  // shots whose Born weights are pending
@@ -416,6 +417,8 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
       (rc = salloc(c, &c->W, items * M)) ||
       (rc = salloc(c, &c->ptab, (int64_t)c->nw * M)) ||
       (rc = salloc(c, &c->sstab, (int64_t)c->nw * M)) ||
+      (rc = salloc(c, &c->ptab64, (int64_t)c->nw * M)) ||
+      (rc = salloc(c, &c->sstab64, (int64_t)c->nw * M)) ||
       (rc = salloc(c, &c->wav, items)) ||
       (rc = salloc(c, &c->rec, (int64_t)g.q_max * g.nrec_max)) ||
       (rc = salloc(c, &c->colptr, (int64_t)g.q_max * (N + 1))) ||
@@ -474,7 +477,10 @@ int brls_ssf_open(const brls_ssf_grid* gin, const float* vel, void* stream,
   a.nshots = 0;
   a.ptab = c->ptab;
   a.sstab = c->sstab;
-  if (launch_ssf_tables(a, c->ptab, c->sstab, c->st) != hipSuccess ||
+  a.ptab64 = c->ptab64;
+  a.sstab64 = c->sstab64;
+  if (launch_ssf_tables(a, c->ptab, c->sstab, c->ptab64, c->sstab64,
+                        c->st) != hipSuccess ||
       hipStreamSynchronize(c->st) != hipSuccess)
     return bail(sfail(c, BRLS_EDEVICE, "building the phase tables failed"));
   *out = c;

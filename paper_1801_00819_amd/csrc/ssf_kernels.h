@@ -32,6 +32,8 @@ struct SsfArgs {
   float2* W;            // [q_max][nw][nz][nx] Born weights
   const float2* ptab;   // [nw][nz][nx] wavenumber-domain phase / nx
   const float2* sstab;  // [nw][nz][nx] split-step phase times taper
+  const double2* ptab64;   // [nw][nz][nx] e^{-i kz dz} (source march)
+  const double2* sstab64;  // [nw][nz][nx] e^{-i w theta} (source march)
   const int* rec;       // [q_max][nrec_max] receiver columns
   const int* colptr;    // [q_max][nx + 1] receivers per column (CSR)
   const int* cidx;      // [q_max][nrec_max] receiver index per CSR entry
@@ -39,8 +41,10 @@ struct SsfArgs {
   int nshots;
 };
 
-// The phase tables of the medium (once per context).
+// The phase tables of the medium (once per context): float ones for A and
+// A^T, double ones for the source march.
 hipError_t launch_ssf_tables(const SsfArgs& a, float2* ptab, float2* sstab,
+                             double2* ptab64, double2* sstab64,
                              hipStream_t st);
 // Born weights of the listed shots (slot and source column of each) for
 // every frequency and level.
