@@ -96,6 +96,37 @@ def test_3d_window_solve_matches_oracle(case):
     ctx.close()
 
 
+def test_3d_full_size_shot_matches_oracle():
+    """Shot 0 of the 256 x 320 x 320 workload at full spatial size (296 x
+    360 x 360 padded, 128 x 128 receivers) in the bench's launch choice
+    (tile variant 0, background checkpointed every 45 steps), for its first
+    120 time steps so the oracle finishes in about half a minute: A m and
+    A^T r against the oracle, m a smoothed seeded Gaussian field (the early
+    wavefield only reaches the top cells, where the layered reflectivity is
+    zero), r seeded Gaussian samples."""
+    import bench
+    from scipy.ndimage import gaussian_filter
+    w = synth.layered3d_256x320x320()
+    s0 = w.shots[0]
+    nt = 120
+    shot = synth.Shot(0, s0.src, s0.rec, nt, s0.f0)
+    m = f32(gaussian_filter(synth.gaussian(w.model_shape, 11), 3.0))
+    r = f32(synth.gaussian((nt, s0.nrec), 12))
+    print("256x320x320 shot 0, 120 steps, bench launch choice", flush=True)
+    ctx = open_ctx(w, q_max=1, ckpt_interval=-1)
+    ctx.set_tile(bench.DEFAULT_TILE3)
+    ctx.update(0, shot.src, shot.rec, nt, shot.f0, None)
+    d = np.asarray(ctx.apply_born(m)).reshape(nt, s0.nrec)
+    g = np.asarray(ctx.apply_adjoint(r.ravel()))
+    ctx.close()
+    prob = oracle_problem(w, shots=[shot])
+    want_d = prob.born_shot(0, m.astype(np.float64))
+    want_g = prob.adjoint_shot(0, r.astype(np.float64))
+    eb, ea = rel(d, want_d), rel(g, want_g)
+    print(f"full-size 3-D shot: born {eb:.2e} adjoint {ea:.2e}", flush=True)
+    assert eb <= 1e-5 and ea <= 1e-5
+
+
 def test_3d_full_size_dot_product():
     """<A m1, d> = <m1, A^T d> on the 256 x 320 x 320 model (padded
     296 x 360 x 360), 128 x 128 receivers, nt = 2000, two shots,
