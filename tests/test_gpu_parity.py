@@ -451,6 +451,44 @@ def test_full_size_adjoint_shot_matches_oracle(P, big):
     assert rel(got, want) <= OP_TOL
 
 
+def test_full_size_ragged_stream_window_matches_oracle(P):
+    """The first window of the 512 x 1024 streaming workload at full size:
+    8 shots of nt 2000 / 3000 / 4000 and 304 .. 1022 receivers in one
+    batched launch sequence, the bench's launch choice, graph mode. Born of
+    the model for the shortest and the longest shot, and the adjoint of a
+    residual carried by the longest one, against the oracle."""
+    w = synth.stream2d_512x1024(nshots=8, Q=8)
+    idx = w.windows()[0]
+    print("512x1024 ragged streaming window, bench launch choice",
+          flush=True)
+    ctx = open_ctx(w, q_max=8)
+    ctx.set_tuning(*_bench_tuning())
+    for i in idx:
+        add_shot(ctx, w, i)
+    m32 = f32(w.m_true)
+    got = split(w, idx, ctx.apply_born(m32))
+    long_i = max(idx, key=lambda i: w.shots[i].nt)
+    s = w.shots[long_i]
+    r = f32(synth.gaussian((s.nt, s.nrec), 91))
+    parts = [np.zeros(w.shots[i].nt * w.shots[i].nrec, np.float32)
+             for i in idx]
+    parts[idx.index(long_i)] = r.ravel()
+    g = ctx.apply_adjoint(np.concatenate(parts))
+    ctx.close()
+    short_i = min(idx, key=lambda i: w.shots[i].nt)
+    for i in (short_i, long_i):
+        prob = oracle_problem(w, shots=[w.shots[i]])
+        want = prob.born_shot(0, m32.astype(np.float64))
+        e = rel(got[idx.index(i)], want)
+        print(f"shot {i} (nt {w.shots[i].nt}, {w.shots[i].nrec} receivers):"
+              f" born {e:.2e}", flush=True)
+        assert e <= OP_TOL
+    prob = oracle_problem(w, shots=[s])
+    e = rel(g, prob.adjoint_shot(0, r.astype(np.float64)))
+    print(f"shot {long_i} adjoint {e:.2e}", flush=True)
+    assert e <= OP_TOL
+
+
 def test_full_size_kernel_forms_agree(P, big):
     """The staged-tile and z-marching kernels on the whole 8-shot window of
     the 512 x 1024 model: the same arithmetic, so the operators agree to a
