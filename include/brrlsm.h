@@ -157,17 +157,30 @@ int brls_window_data_size(const brls_ctx* ctx, int64_t* n);
  * with brls_set_regularization mode 1 the damping term is
  * lambda (m - m_start); with brls_set_precond mode 1 the CG is
  * preconditioned).
- * Vectors are float32; the CG scalars (alpha, beta, norms) are float64.
+ * Vectors are float64 (float32 with brls_set_precision); the CG scalars
+ * (alpha, beta, norms) are float64.
  * An empty window or a zero gradient returns at once with iters = 0.
  * stats may be NULL. Errors: BRLS_EBREAKDOWN, BRLS_ENONFINITE. */
 int brls_solve_window(brls_ctx* ctx, int32_t max_iter, double rtol,
                       brls_stats* stats);
 
-/* Copy the current image [nz][ny][nx] out (synchronises the stream). */
+/* Copy the current image [nz][ny][nx] out (synchronises the stream): the
+ * window's solution of eq. 10, m after the last window being the chain's
+ * result (Fig. 2d). */
 int brls_image(brls_ctx* ctx, float* out);
 
-/* Set the current image (e.g. resume, or an explicit start). */
+/* Set the current image: the start of the next solve (eq. 11's warm start
+ * from a given image, or m = 0 to start afresh). */
 int brls_set_image(brls_ctx* ctx, const float* m);
+
+/* The same in float64. With float64 CG vectors (brls_set_precision) the
+ * image is kept in float64 between solves, so the chain's state is this
+ * image and the window: a chain interrupted after a window and resumed
+ * with brls_set_image64 of brls_image64's output continues bitwise as if
+ * uninterrupted (brls_set_image rounds it to float32 first). out / m:
+ * host or device [nz][ny][nx] doubles per flags. */
+int brls_image64(brls_ctx* ctx, double* out);
+int brls_set_image64(brls_ctx* ctx, const double* m);
 
 /* Preconditioner of brls_solve_window. The paper asks for one in each
  * window's CG (to cluster the normal operator's eigenvalues near 1) and
@@ -188,6 +201,24 @@ int brls_get_precond(const brls_ctx* ctx, int32_t* mode);
  * Other modes: BRLS_EINVAL. */
 int brls_set_regularization(brls_ctx* ctx, int32_t mode);
 int brls_get_regularization(const brls_ctx* ctx, int32_t* mode);
+
+/* Arithmetic precision of two parts of the path (bits, 32 or 64 each).
+ * background: the background wavefield u0 of each shot entering the window
+ *   (the reference field of eq. 1's linearisation, computed once per shot),
+ *   advanced in float64 and its Born-source frames D2u0^n stored in float32
+ *   (64, the default with stored Born sources), or advanced in float32 by
+ *   the stencil kernels (32; the only choice with checkpoints). Changing it
+ *   rebuilds the window's stored sources at the next operator call.
+ * vectors: the CG vectors of brls_solve_window (eq. 10's m, the search
+ *   direction, the gradient and the residual) in float64 (64, the default)
+ *   or float32 (32). The operators always take float32 inputs and
+ *   propagate float32 wavefields; the CG scalars are float64 either way.
+ * Both guard the final image of a truncated window solve, which amplifies
+ * rounding of its inputs (eqs. 10-11). Errors: BRLS_EINVAL (other values;
+ * background 64 with checkpoints). */
+int brls_set_precision(brls_ctx* ctx, int32_t background, int32_t vectors);
+int brls_get_precision(const brls_ctx* ctx, int32_t* background,
+                       int32_t* vectors);
 
 /* Misfit weight of one window shot (default 1, reset by brls_update): the
  * window solve minimises sum_j w_j ||A_j m - d_j||^2 + the damping term,

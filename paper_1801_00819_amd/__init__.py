@@ -30,27 +30,29 @@ __all__ = [
 ]
 
 
-def _ptr(a, device: bool, n: Optional[int] = None):
-    """Pointer to a float32 buffer the library reads or writes: a contiguous
-    CUDA tensor (device context) or a C-contiguous ndarray (host context)
-    holding at least ``n`` floats."""
+def _ptr(a, device: bool, n: Optional[int] = None, bits: int = 32):
+    """Pointer to a float32 (``bits`` 64: float64) buffer the library reads
+    or writes: a contiguous CUDA tensor (device context) or a C-contiguous
+    ndarray (host context) holding at least ``n`` elements."""
     if a is None:
         return None
     if device:
         import torch
+        want = torch.float32 if bits == 32 else torch.float64
         if not (isinstance(a, torch.Tensor) and a.is_cuda):
             raise TypeError("device context: pass a CUDA tensor")
-        if a.dtype != torch.float32:
-            raise TypeError(f"tensor must be float32, got {a.dtype}")
+        if a.dtype != want:
+            raise TypeError(f"tensor must be {want}, got {a.dtype}")
         if not a.is_contiguous():
             raise ValueError("tensor must be contiguous")
         size = a.numel()
         ptr = a.data_ptr()
     else:
-        if not (isinstance(a, np.ndarray) and a.dtype == np.float32
+        want = np.float32 if bits == 32 else np.float64
+        if not (isinstance(a, np.ndarray) and a.dtype == want
                 and a.flags.c_contiguous):
-            raise TypeError("host context: pass a C-contiguous float32 "
-                            "ndarray")
+            raise TypeError(f"host context: pass a C-contiguous "
+                            f"{np.dtype(want).name} ndarray")
         size = a.size
         ptr = a.ctypes.data
     if n is not None and size < n:
@@ -68,6 +70,9 @@ class Context:
         self.device = device
         self._keep = []
         self._data_size = {}  # shot id -> nt * nrec
+        # bumped by every update and downdate: the window (and so the
+        # operator) a result belongs to
+        self.generation = 0
 
     # ------------------------------------------------------------------
     def close(self):
@@ -100,12 +105,14 @@ class Context:
         sh.data = p.value if p is not None else None
         self._check(L.lib().brls_update(self._h, ctypes.byref(sh)))
         self._data_size[int(id)] = sh.nt * sh.nrec
+        self.generation += 1
 
     update = brls_update
 
     def brls_downdate(self, id: int):
         self._check(L.lib().brls_downdate(self._h, int(id)))
         self._data_size.pop(int(id), None)
+        self.generation += 1
 
     downdate = brls_downdate
 
@@ -170,6 +177,30 @@ class Context:
 
     set_image = brls_set_image
 
+    def brls_image64(self, out=None):
+        """The current image in float64 (the chain's full state with float64
+        CG vectors)."""
+        if out is None:
+            if self.device:
+                import torch
+                out = torch.empty(self.model_shape, dtype=torch.float64,
+                                  device="cuda")
+            else:
+                out = np.empty(self.model_shape, np.float64)
+        self._check(L.lib().brls_image64(
+            self._h, _ptr(out, self.device, self.model_size, 64)))
+        return out
+
+    image64 = brls_image64
+
+    def brls_set_image64(self, m):
+        if not self.device:
+            m = np.ascontiguousarray(m, dtype=np.float64)
+        self._check(L.lib().brls_set_image64(
+            self._h, _ptr(m, self.device, self.model_size, 64)))
+
+    set_image64 = brls_set_image64
+
     def brls_set_precond(self, mode: int):
         """0: plain CG; 1: diagonal illumination preconditioner."""
         self._check(L.lib().brls_set_precond(self._h, int(mode)))
@@ -182,6 +213,22 @@ class Context:
         self._check(L.lib().brls_set_regularization(self._h, int(mode)))
 
     set_regularization = brls_set_regularization
+
+    def brls_set_precision(self, background: int = 64, vectors: int = 64):
+        """Bits of the background wavefield of new shots (64 needs stored
+        Born sources) and of the CG vectors: 32 or 64 each."""
+        self._check(L.lib().brls_set_precision(self._h, int(background),
+                                               int(vectors)))
+
+    set_precision = brls_set_precision
+
+    def brls_get_precision(self):
+        b, v = ctypes.c_int32(), ctypes.c_int32()
+        self._check(L.lib().brls_get_precision(self._h, ctypes.byref(b),
+                                               ctypes.byref(v)))
+        return b.value, v.value
+
+    get_precision = brls_get_precision
 
     def brls_set_shot_weight(self, id: int, w: float):
         """Misfit weight of a window shot (1 by default; beta^age gives the

@@ -101,8 +101,13 @@ SIGNATURES = [
                                  ctypes.POINTER(brls_stats)]),
     ("brls_image", _I32, [_VP, _VP]),
     ("brls_set_image", _I32, [_VP, _VP]),
+    ("brls_image64", _I32, [_VP, _VP]),
+    ("brls_set_image64", _I32, [_VP, _VP]),
     ("brls_set_precond", _I32, [_VP, _I32]),
     ("brls_set_regularization", _I32, [_VP, _I32]),
+    ("brls_set_precision", _I32, [_VP, _I32, _I32]),
+    ("brls_get_precision", _I32, [_VP, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]),
     ("brls_set_shot_weight", _I32, [_VP, ctypes.c_int64, ctypes.c_double]),
     ("brls_get_shot_weight", _I32,
      [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),

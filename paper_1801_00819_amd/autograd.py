@@ -32,10 +32,17 @@ class BornFn(torch.autograd.Function):
         if not lib_ctx.device:
             raise ValueError("BornFn needs a context opened with device=True")
         fctx.lib_ctx = lib_ctx
+        fctx.generation = lib_ctx.generation
         return lib_ctx.apply_born(m.detach().contiguous())
 
     @staticmethod
     def backward(fctx, grad_d: torch.Tensor):
+        # the adjoint must belong to the window the forward pass modelled
+        if fctx.lib_ctx.generation != fctx.generation:
+            raise RuntimeError(
+                "BornFn.backward: the context's window changed (update or "
+                "downdate) after the forward pass; the adjoint would belong "
+                "to another operator")
         g = fctx.lib_ctx.apply_adjoint(grad_d.detach().contiguous())
         return g, None
 

@@ -1,5 +1,6 @@
 // Vector kernels of the CG solver: fills, axpy-type updates and dot
-// products of float32 vectors accumulated in float64.
+// products of float32 vectors accumulated in float64, and the same for the
+// solver's float64 vectors.
 //
 // Dot products run in two fixed-order stages (kDotBlocks per-block partial
 // sums, then a single block), so a result does not depend on scheduling and
@@ -138,6 +139,72 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// ---- float64 CG vectors ----------------------------------------------------
+#define GRID_STRIDE(i, n)                                                   \
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); \
+       i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void k_cvt_f2d(double* y, const float* x, int64_t n) {
+  GRID_STRIDE(i, n) y[i] = (double)x[i];
+}
+
+__global__ void k_cvt_d2f(float* y, const double* x, const float* w,
+                          int64_t seg, int64_t n) {
+  if (w) {
+    GRID_STRIDE(i, n) y[i] = (float)((double)w[i / seg] * x[i]);
+  } else {
+    GRID_STRIDE(i, n) y[i] = (float)x[i];
+  }
+}
+
+__global__ void k_sub_d(double* r, const float* d, const float* q,
+                        int64_t n) {
+  GRID_STRIDE(i, n) r[i] = (double)d[i] - (double)q[i];
+}
+
+__global__ void k_axpy_dd(double* y, const double* x, double alpha,
+                          int64_t n) {
+  GRID_STRIDE(i, n) y[i] = fma(alpha, x[i], y[i]);
+}
+
+__global__ void k_axpy_df(double* y, const float* x, double alpha,
+                          int64_t n) {
+  GRID_STRIDE(i, n) y[i] = fma(alpha, (double)x[i], y[i]);
+}
+
+__global__ void k_xpby_d(double* p, const double* s, double beta,
+                         int64_t n) {
+  GRID_STRIDE(i, n) p[i] = fma(beta, p[i], s[i]);
+}
+
+__global__ void __launch_bounds__(256)
+    k_grad_norm_d(double* s, const double* g, const double* m, double lambda,
+                  int64_t n, double* part) {
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const double v = g[i] - lambda * m[i];
+    s[i] = v;
+    acc = fma(v, v, acc);
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256)
+    k_dot_partial_d(const double* a, const double* b, int64_t n,
+                    double* part) {
+  double acc = 0.0;
+  GRID_STRIDE(i, n) acc = fma(a[i], b[i], acc);
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_mul_fd(double* z, const float* a, const double* b,
+                         int64_t n) {
+  GRID_STRIDE(i, n) z[i] = (double)a[i] * b[i];
+}
+#undef GRID_STRIDE
+
 static int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 8192) b = 8192;
@@ -244,6 +311,79 @@ hipError_t launch_nonfinite(const float* x, int64_t n, int* flag,
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(n)), dim3(256), 0, st, x, n,
                      flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_cvt_f2d(double* y, const float* x, int64_t n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cvt_f2d, dim3(grid_for(n)), dim3(256), 0, st, y, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cvt_d2f(float* y, const double* x, const float* w,
+                          int64_t seg, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cvt_d2f, dim3(grid_for(n)), dim3(256), 0, st, y, x, w,
+                     seg, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_d(double* r, const float* d, const float* q, int64_t n,
+                        hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_d, dim3(grid_for(n)), dim3(256), 0, st, r, d, q, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dd(double* y, const double* x, double alpha, int64_t n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy_dd, dim3(grid_for(n)), dim3(256), 0, st, y, x,
+                     alpha, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_df(double* y, const float* x, double alpha, int64_t n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy_df, dim3(grid_for(n)), dim3(256), 0, st, y, x,
+                     alpha, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby_d(double* p, const double* s, double beta, int64_t n,
+                         hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xpby_d, dim3(grid_for(n)), dim3(256), 0, st, p, s,
+                     beta, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_norm_d(double* s, const double* g, const double* m,
+                              double lambda, int64_t n, double* partial,
+                              double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_norm_d, dim3(kDotBlocks), dim3(256), 0, st, s, g,
+                     m, lambda, n, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial,
+                     kDotBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_d(const double* a, const double* b, int64_t n,
+                        double* partial, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_partial_d, dim3(kDotBlocks), dim3(256), 0, st, a,
+                     b, n, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial,
+                     kDotBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul_fd(double* z, const float* a, const double* b,
+                         int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mul_fd, dim3(grid_for(n)), dim3(256), 0, st, z, a, b,
+                     n);
   return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ struct Slot {
   float* ck = nullptr;       // [nseg][u | v][field] (checkpoint mode)
   float* segd2 = nullptr;    // [ckpt_k][nz][nx] (checkpoint mode)
   float* wav = nullptr;      // [nt_max]
+  double* wav64 = nullptr;   // [nt_max] (float64 background)
   float* illum = nullptr;    // [nz][nx] sum of squared Born sources (cache)
   bool illum_ready = false;  // illum holds this shot's sum
   int* rptr = nullptr;       // [ntiles_max + 1]
@@ -116,6 +117,16 @@ struct brls_ctx {
                           // the image the solve starts from
   float* dm = nullptr;    // that correction (mode 1)
   double* acc = nullptr;
+  // precision (brls_set_precision): float64 background of new shots (stored
+  // Born sources only) and float64 CG vectors
+  int bg64 = 1;
+  int vec64 = 1;
+  double eta_scale64 = 0.0;  // eta_max * dt / 2 / nb^2
+  double* wp64 = nullptr;     // W' in float64, storage layout
+  double* bgf64 = nullptr;    // [q_max][u even | u odd | v] float64 fields
+  Bg64Shot* bg64tab_dev = nullptr;
+  double *m64 = nullptr, *p64 = nullptr, *s64 = nullptr, *g64 = nullptr,
+         *dm64 = nullptr, *z64 = nullptr, *r64 = nullptr;
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr;
   float* wslot = nullptr;  // [q_max] per-slot misfit weights (device)
   std::vector<float> wslot_h;  // their host copy, uploaded by the solve
@@ -422,6 +433,29 @@ int nseg_of(const brls_ctx* c, int nt) {
   return (nt - 1 + c->ckpt_k - 1) / c->ckpt_k;
 }
 
+Bg64Args bg64_args(const brls_ctx* c) {
+  Bg64Args a{};
+  a.ndim = c->ndim;
+  a.nb = c->g.nb;
+  a.nz = c->g.nz;
+  a.ny = c->ndim == 3 ? c->g.ny : 1;
+  a.nx = c->g.nx;
+  a.pz = a.nz + 2 * a.nb;
+  a.py = c->ndim == 3 ? a.ny + 2 * a.nb : 1;
+  a.px = a.nx + 2 * a.nb;
+  a.pitch = c->ndim == 3 ? c->geo3.pitch : c->geo.pitch;
+  a.xoff = c->ndim == 3 ? c->geo3.xoff : c->geo.xoff;
+  a.plane = c->ndim == 3 ? c->geo3.plane : 0;
+  a.mplane = c->mplane;
+  a.eta_scale = c->eta_scale64;
+  a.w[0] = kW1;
+  a.w[1] = kW2;
+  a.w[2] = kW3;
+  a.w[3] = kW4;
+  a.wp = c->wp64;
+  return a;
+}
+
 // Background wavefields (and Born-source caches) of shots that lack them.
 int ensure_backgrounds(brls_ctx* c) {
   std::vector<int> todo;
@@ -442,6 +476,37 @@ int ensure_backgrounds(brls_ctx* c) {
   }
   const int ntm = nt_max_of(c, todo);
   const int nsh = (int)todo.size();
+  if (!c->ckpt_k && c->bg64) {
+    // float64 background, one batched launch per time step (the fields of
+    // the k-th shot to build in the k-th triple of bgf64)
+    std::vector<Bg64Shot> bt(nsh);
+    for (int k = 0; k < nsh; ++k) {
+      const Slot& sl = c->slots[todo[k]];
+      double* f = c->bgf64 + (int64_t)k * 3 * c->fs;
+      bt[k].u[0] = f;
+      bt[k].u[1] = f + c->fs;
+      bt[k].v = f + 2 * c->fs;
+      bt[k].d2 = sl.d2;
+      bt[k].wav = sl.wav64;
+      bt[k].nt = sl.nt;
+      bt[k].src_z = sl.sz + c->g.nb;
+      bt[k].src_y = c->ndim == 3 ? sl.sy + c->g.nb : 0;
+      bt[k].src_x = sl.sx + c->g.nb;
+    }
+    HIPCHECK(c, hipMemcpy(c->bg64tab_dev, bt.data(), sizeof(Bg64Shot) * nsh,
+                          hipMemcpyHostToDevice));
+    HIPCHECK(c, launch_fill_f64(c->bgf64, (int64_t)nsh * 3 * c->fs, 0.0,
+                                c->st));
+    const Bg64Args ba = bg64_args(c);
+    for (int n = 0; n + 1 < ntm; ++n)
+      HIPCHECK(c, launch_background64(ba, c->bg64tab_dev, nsh, n, c->st));
+    HIPCHECK(c, hipStreamSynchronize(c->st));
+    for (int i : todo) {
+      c->slots[i].bg_ready = true;
+      c->slots[i].illum_ready = false;
+    }
+    return BRLS_OK;
+  }
   // cache mode: every Born-source frame stored; checkpoint mode: the state
   // every ckpt_k steps
   const int wr = c->ckpt_k ? 0 : 1;
@@ -610,10 +675,11 @@ int enqueue_adjoint(brls_ctx* c, int batched) {
                    : adjoint_steps(c, c->tab_dev, nsh, pb, ntm - 1, 1, 0);
     if (rc) return rc;
   }
-  HIPCHECK(c, c->ndim == 3 ? launch_adj_finalize3(c->acc, ngroups, c->geo3,
-                                                   c->wp, c->gbuf, c->st)
-                           : launch_adj_finalize(c->acc, ngroups, c->geo,
-                                                 c->wp, c->gbuf, c->st));
+  HIPCHECK(c, c->ndim == 3
+                  ? launch_adj_finalize3(c->acc, ngroups, c->geo3, c->wp,
+                                         c->gbuf, c->g64, c->st)
+                  : launch_adj_finalize(c->acc, ngroups, c->geo, c->wp,
+                                        c->gbuf, c->g64, c->st));
   return BRLS_OK;
 }
 
@@ -777,8 +843,8 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   c->device = dev;
   c->ndim = g.ndim;
   const double eta_max = 3.0 * vmax * std::log(1000.0) / (2.0 * g.nb * g.h);
-  const float eta_scale =
-      (float)(eta_max * g.dt / 2.0 / ((double)g.nb * g.nb));
+  c->eta_scale64 = eta_max * g.dt / 2.0 / ((double)g.nb * g.nb);
+  const float eta_scale = (float)c->eta_scale64;
   const StencilW sw = {(float)kW1, (float)kW2, (float)kW3, (float)kW4};
   const int x_org = (g.nb % 32 == 0) ? 0 : (g.nb % 32) - 32;
   const int px = g.nx + 2 * g.nb;
@@ -839,6 +905,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   else
     c->ckpt_k = g.ckpt_interval;
   if (c->ckpt_k) c->nseg_max = (g.nt_max - 1 + c->ckpt_k - 1) / c->ckpt_k;
+  if (c->ckpt_k) c->bg64 = 0;  // the background is recomputed in float32
   if (c->fs >= lim) {  // the storage ring and pitch padding on top
     brls_close(c);
     return fail(nullptr, BRLS_EINVAL,
@@ -865,6 +932,18 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   ALLOC(c->z, mpts);
   ALLOC(c->dm, mpts);
   ALLOC(c->acc, (int64_t)g.q_max * mpts);
+  ALLOC(c->m64, mpts);
+  ALLOC(c->p64, mpts);
+  ALLOC(c->s64, mpts);
+  ALLOC(c->g64, mpts);
+  ALLOC(c->dm64, mpts);
+  ALLOC(c->z64, mpts);
+  ALLOC(c->r64, (int64_t)g.q_max * c->seg);
+  if (!c->ckpt_k) {
+    ALLOC(c->wp64, c->fs);
+    ALLOC(c->bgf64, (int64_t)g.q_max * 3 * c->fs);
+    ALLOC(c->bg64tab_dev, g.q_max);
+  }
   ALLOC(c->dobs, (int64_t)g.q_max * c->seg);
   ALLOC(c->r, (int64_t)g.q_max * c->seg);
   ALLOC(c->q, (int64_t)g.q_max * c->seg);
@@ -891,6 +970,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
       ALLOC(sl.illum, mpts);
     }
     ALLOC(sl.wav, g.nt_max);
+    if (!c->ckpt_k) ALLOC(sl.wav64, g.nt_max);
     ALLOC(sl.rptr, c->ntiles_max + 1);
     // a receiver lies in up to 4 tiles' widened regions (two-step tiles)
     ALLOC(sl.rent, (int64_t)g.nrec_max * (g.ndim == 2 ? 4 : 1));
@@ -899,6 +979,7 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
 #undef ALLOC
   // W' = v^2 dt^2 / h^2 on the padded grid (velocity edge-replicated)
   std::vector<float> wh((size_t)c->fs, 0.f);
+  std::vector<double> wh64(c->ckpt_k ? 0 : (size_t)c->fs, 0.0);
   const double s2 = g.dt * g.dt / (g.h * g.h);
   const int pz = g.nz + 2 * g.nb, py = g.ndim == 3 ? ny + 2 * g.nb : 1;
   for (int z = 0; z < pz; ++z)
@@ -910,12 +991,18 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
         const int mx = std::min(std::max(x - g.nb, 0), g.nx - 1);
         const double v = vel[((int64_t)mz * ny + my) * g.nx + mx];
         wh[store_index(c, z, y, x)] = (float)(v * v * s2);
+        if (!wh64.empty()) wh64[store_index(c, z, y, x)] = v * v * s2;
       }
   auto init = [&]() -> int {
     HIPCHECK(c, hipMemcpy(c->wp, wh.data(), sizeof(float) * wh.size(),
                           hipMemcpyHostToDevice));
     HIPCHECK(c, launch_fill_f32(c->fields_all, field_floats(c), 0.f, c->st));
+    if (!wh64.empty())
+      HIPCHECK(c, hipMemcpy(c->wp64, wh64.data(),
+                            sizeof(double) * wh64.size(),
+                            hipMemcpyHostToDevice));
     HIPCHECK(c, launch_fill_f32(c->m, mpts, 0.f, c->st));
+    HIPCHECK(c, launch_fill_f64(c->m64, mpts, 0.0, c->st));
     for (float* v : {c->dobs, c->r, c->q, c->dscr})
       HIPCHECK(c, launch_fill_f32(v, (int64_t)g.q_max * c->seg, 0.f, c->st));
     HIPCHECK(c, hipStreamSynchronize(c->st));
@@ -1006,11 +1093,13 @@ int brls_update(brls_ctx* c, const brls_shot* sh) {
   // h^2 * Ricker(f0), delay 1.5/f0: the point source of strength h^d f(t)
   // scaled to the W' = v^2 dt^2 / h^2 of the kernels.
   std::vector<float> wav(sh->nt);
+  std::vector<double> wav64(sh->nt);
   const double t0 = 1.5 / sh->f0, pi = 3.14159265358979323846;
   for (int n = 0; n < sh->nt; ++n) {
     const double t = n * c->g.dt - t0;
     const double a = pi * pi * sh->f0 * sh->f0 * t * t;
-    wav[n] = (float)(c->g.h * c->g.h * (1.0 - 2.0 * a) * std::exp(-a));
+    wav64[n] = c->g.h * c->g.h * (1.0 - 2.0 * a) * std::exp(-a);
+    wav[n] = (float)wav64[n];
   }
   std::vector<int> rs(sh->nrec);
   for (int j = 0; j < sh->nrec; ++j)
@@ -1019,6 +1108,9 @@ int brls_update(brls_ctx* c, const brls_shot* sh) {
                              sl.rec[3 * j + 2] + c->g.nb);
   HIPCHECK(c, hipMemcpyAsync(sl.wav, wav.data(), 4 * wav.size(),
                              hipMemcpyHostToDevice, c->st));
+  if (sl.wav64)
+    HIPCHECK(c, hipMemcpyAsync(sl.wav64, wav64.data(), 8 * wav64.size(),
+                               hipMemcpyHostToDevice, c->st));
   HIPCHECK(c, hipMemcpyAsync(sl.rsidx, rs.data(), 4 * rs.size(),
                              hipMemcpyHostToDevice, c->st));
   int rc = build_receiver_tiles(c, sl);  // synchronises
@@ -1079,6 +1171,122 @@ int brls_window_data_size(const brls_ctx* c, int64_t* n) {
   return BRLS_OK;
 }
 
+namespace {
+
+// brls_solve_window with float64 CG vectors: m, p, s (and the correction,
+// the preconditioned direction) on the model, r on the data, all float64;
+// the operators take float32 copies of p (or m) and of r (times the shot
+// weights), and the adjoint's float64 image sum is taken before rounding.
+// Same recurrences and stop test as the float32 form.
+int solve_window64(brls_ctx* c, int32_t max_iter, double rtol,
+                   brls_stats* st, bool weighted) {
+  const double lam = c->g.lambda;
+  const int64_t M = c->mplane, D = (int64_t)c->g.q_max * c->seg;
+  const float* wts = weighted ? c->wslot : nullptr;
+  double sc[2];
+  int rc;
+  // A x for a float64 model vector x
+  auto born64 = [&](const double* x) -> int {
+    HIPCHECK(c, launch_cvt_d2f(c->born_in, x, nullptr, 1, M, c->st));
+    return born_of(c, c->born_in);
+  };
+  // A^T W x for a float64 data vector x; the image lands in g64
+  auto adjoint64 = [&](const double* x) -> int {
+    HIPCHECK(c, launch_cvt_d2f(c->dscr, x, wts, c->seg, D, c->st));
+    return adjoint_of(c, c->dscr);
+  };
+  // r = d - A m (m64 is the image, kept between solves: a warm start is
+  // not rounded to float32)
+  if ((rc = born64(c->m64))) return rc;
+  HIPCHECK(c, launch_sub_d(c->r64, c->dobs, c->q, D, c->st));
+  const bool corr = c->regularize == 1;
+  if (corr) HIPCHECK(c, launch_fill_f64(c->dm64, M, 0.0, c->st));
+  const double* damped = corr ? c->dm64 : c->m64;
+  if ((rc = adjoint64(c->r64))) return rc;
+  HIPCHECK(c, launch_grad_norm_d(c->s64, c->g64, damped, lam, M, c->partial,
+                                 c->scal, c->st));
+  if ((rc = read_scalars(c, sc, 1))) return rc;
+  double gamma = sc[0];
+  if (!std::isfinite(gamma))
+    return fail(c, BRLS_ENONFINITE, "non-finite gradient norm");
+  st->s0_norm = std::sqrt(gamma);
+  st->s_norm = st->s0_norm;
+  double ref = 0.0;
+  if (rtol > 0) {
+    // ||A^T W d||: the observed data are float32 already
+    if (weighted) {
+      HIPCHECK(c, launch_scale_segments(c->dscr, c->dobs, c->wslot, c->seg, D,
+                                        c->st));
+      if ((rc = adjoint_of(c, c->dscr))) return rc;
+    } else if ((rc = adjoint_of(c, c->dobs))) {
+      return rc;
+    }
+    HIPCHECK(c, launch_dot_d(c->g64, c->g64, M, c->partial, c->scal, c->st));
+    if ((rc = read_scalars(c, sc, 1))) return rc;
+    ref = std::sqrt(sc[0]);
+    st->ref_norm = ref;
+  }
+  double snorm = std::sqrt(gamma);
+  const bool pre = c->precond != 0;
+  if (pre) {
+    if ((rc = build_minv(c))) return rc;
+    HIPCHECK(c, launch_mul_fd(c->z64, c->minv, c->s64, M, c->st));
+    HIPCHECK(c, launch_dot_d(c->s64, c->z64, M, c->partial, c->scal, c->st));
+    if ((rc = read_scalars(c, sc, 1))) return rc;
+    gamma = sc[0];
+  }
+  HIPCHECK(c, hipMemcpyAsync(c->p64, pre ? c->z64 : c->s64, M * 8,
+                             hipMemcpyDeviceToDevice, c->st));
+  for (int it = 0; it < max_iter; ++it) {
+    if (gamma == 0.0) break;
+    if (rtol > 0 && snorm <= rtol * ref) break;
+    if ((rc = born64(c->p64))) return rc;
+    if (weighted)
+      HIPCHECK(c, launch_scale_segments(c->dscr, c->q, c->wslot, c->seg, D,
+                                        c->st));
+    HIPCHECK(c, launch_dot(c->q, weighted ? c->dscr : c->q, D, c->partial,
+                           c->scal, c->st));
+    HIPCHECK(c, launch_dot_d(c->p64, c->p64, M, c->partial, c->scal + 1,
+                             c->st));
+    if ((rc = read_scalars(c, sc, 2))) return rc;
+    const double delta = sc[0] + lam * sc[1];
+    if (!std::isfinite(delta))
+      return fail(c, BRLS_ENONFINITE, "non-finite CG scalar delta");
+    if (!(delta > 0.0))
+      return fail(c, BRLS_EBREAKDOWN, "CG breakdown: delta = %g", delta);
+    const double alpha = gamma / delta;
+    HIPCHECK(c, launch_axpy_dd(c->m64, c->p64, alpha, M, c->st));
+    if (corr) HIPCHECK(c, launch_axpy_dd(c->dm64, c->p64, alpha, M, c->st));
+    HIPCHECK(c, launch_axpy_df(c->r64, c->q, -alpha, D, c->st));
+    if ((rc = adjoint64(c->r64))) return rc;
+    HIPCHECK(c, launch_grad_norm_d(c->s64, c->g64, damped, lam, M,
+                                   c->partial, c->scal, c->st));
+    if (pre) {
+      HIPCHECK(c, launch_mul_fd(c->z64, c->minv, c->s64, M, c->st));
+      HIPCHECK(c, launch_dot_d(c->s64, c->z64, M, c->partial, c->scal + 1,
+                               c->st));
+    }
+    if ((rc = read_scalars(c, sc, pre ? 2 : 1))) return rc;
+    const double gnew = pre ? sc[1] : sc[0];
+    if (!std::isfinite(sc[0]) || !std::isfinite(gnew))
+      return fail(c, BRLS_ENONFINITE, "non-finite gradient norm");
+    const double beta = gnew / gamma;
+    HIPCHECK(c, launch_xpby_d(c->p64, pre ? c->z64 : c->s64, beta, M, c->st));
+    gamma = gnew;
+    snorm = std::sqrt(sc[0]);
+    st->iters = it + 1;
+    st->s_norm = snorm;
+  }
+  HIPCHECK(c, launch_dot_d(c->r64, c->r64, D, c->partial, c->scal, c->st));
+  if ((rc = read_scalars(c, sc, 1))) return rc;
+  st->r_norm = std::sqrt(sc[0]);
+  // the float32 image mirrors the float64 one
+  HIPCHECK(c, launch_cvt_d2f(c->m, c->m64, nullptr, 1, M, c->st));
+  return BRLS_OK;
+}
+
+}  // namespace
+
 int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
                       brls_stats* stats) {
   if (!c) return BRLS_EINVAL;
@@ -1109,6 +1317,7 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
     HIPCHECK(c, hipMemcpyAsync(c->wslot, c->wslot_h.data(),
                                (size_t)c->g.q_max * 4, hipMemcpyHostToDevice,
                                c->st));
+  if (c->vec64) return finish(solve_window64(c, max_iter, rtol, &st, weighted));
   // adjoint of W x (x itself when unweighted)
   auto adjoint_w = [&](const float* x) -> int {
     if (!weighted) return adjoint_of(c, x);
@@ -1195,6 +1404,7 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
   HIPCHECK(c, launch_dot(c->r, c->r, D, c->partial, c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
   st.r_norm = std::sqrt(sc[0]);
+  HIPCHECK(c, launch_cvt_f2d(c->m64, c->m, M, c->st));
   return finish(BRLS_OK);
 }
 
@@ -1236,6 +1446,33 @@ int brls_set_precond(brls_ctx* c, int32_t mode) {
   return BRLS_OK;
 }
 
+int brls_set_precision(brls_ctx* c, int32_t background, int32_t vectors) {
+  if (!c) return BRLS_EINVAL;
+  if ((background != 32 && background != 64) ||
+      (vectors != 32 && vectors != 64))
+    return fail(c, BRLS_EINVAL, "precision %d / %d: each must be 32 or 64",
+                background, vectors);
+  if (background == 64 && c->ckpt_k)
+    return fail(c, BRLS_EINVAL,
+                "a float64 background needs stored Born sources (checkpoint "
+                "interval 0)");
+  const int bg = background == 64;
+  if (bg != c->bg64) {  // rebuild the window's stored sources
+    for (Slot& sl : c->slots) sl.bg_ready = false;
+    c->bg64 = bg;
+  }
+  c->vec64 = vectors == 64;
+  return BRLS_OK;
+}
+
+int brls_get_precision(const brls_ctx* c, int32_t* background,
+                       int32_t* vectors) {
+  if (!c || !background || !vectors) return BRLS_EINVAL;
+  *background = c->bg64 ? 64 : 32;
+  *vectors = c->vec64 ? 64 : 32;
+  return BRLS_OK;
+}
+
 int brls_set_regularization(brls_ctx* c, int32_t mode) {
   if (!c) return BRLS_EINVAL;
   if (mode != 0 && mode != 1)
@@ -1272,6 +1509,22 @@ int brls_illumination(brls_ctx* c, float* out) {
 int brls_set_image(brls_ctx* c, const float* m) {
   if (!c || !m) return fail(c, BRLS_EINVAL, "NULL argument");
   HIPCHECK(c, hipMemcpyAsync(c->m, m, c->mplane * 4, in_kind(c), c->st));
+  HIPCHECK(c, launch_cvt_f2d(c->m64, c->m, c->mplane, c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_image64(brls_ctx* c, double* out) {
+  if (!c || !out) return fail(c, BRLS_EINVAL, "NULL argument");
+  HIPCHECK(c, hipMemcpyAsync(out, c->m64, c->mplane * 8, out_kind(c), c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
+int brls_set_image64(brls_ctx* c, const double* m) {
+  if (!c || !m) return fail(c, BRLS_EINVAL, "NULL argument");
+  HIPCHECK(c, hipMemcpyAsync(c->m64, m, c->mplane * 8, in_kind(c), c->st));
+  HIPCHECK(c, launch_cvt_d2f(c->m, c->m64, nullptr, 1, c->mplane, c->st));
   HIPCHECK(c, hipStreamSynchronize(c->st));
   return BRLS_OK;
 }

@@ -27,7 +27,7 @@ hipError_t launch_step3d(int variant, int mode, const StepArgs& a,
                          hipStream_t st);
 hipError_t launch_adj_finalize3(const double* acc, int ngroups,
                                 const Geo3D& g, const float* wp, float* out,
-                                hipStream_t st);
+                                double* out64, hipStream_t st);
 
 // Blocks of `kernel` (launched with `threads` per block) that fit on the
 // current device at once.
@@ -51,9 +51,11 @@ hipError_t launch_step2d(int variant, int mode, const StepArgs& a,
 // ceil((nt-1)/2) mod 2, else (nt-1) mod 2).
 hipError_t launch_born_last(const ShotDev* tab, int nshots, int nrec_max,
                             float* dat, int two_step, hipStream_t st);
+// out (and out64 unless NULL) = sum of the accumulators / W' on the model
+// region.
 hipError_t launch_adj_finalize(const double* acc, int ngroups,
                                const Geo2D& g, const float* wp, float* out,
-                               hipStream_t st);
+                               double* out64, hipStream_t st);
 // Background checkpoint save (restore = 0) / restore (1) for all shots.
 hipError_t launch_ckpt(const ShotDev* tab, int nshots, int n0, int seg,
                        int64_t fs, int restore, hipStream_t st);
@@ -100,6 +102,63 @@ hipError_t launch_sum(const float* x, int64_t n, double* partial, double* out,
 hipError_t launch_gather_receivers(const ShotDev* tab, int nshots,
                                    int nrec_max, int n, float* dst,
                                    hipStream_t st);
+// Float64 background of shots entering the window (bg64.hip), stored-source
+// strategy: per shot, u of even / odd levels and v in float64 on the
+// wavefield storage layout, the float32 Born-source frames written on the
+// model region.
+struct Bg64Shot {
+  double* u[2];        // u of even / odd levels
+  double* v;           // u^n - u^{n-1}, updated in place
+  float* d2;           // Born-source frames [nt - 1][model]
+  const double* wav;   // h^2 * source wavelet [nt]
+  int nt;
+  int src_z, src_y, src_x;  // padded grid position of the source
+};
+struct Bg64Args {
+  int ndim;
+  int pz, py, px;      // padded grid (py = 1 in 2-D)
+  int nz, ny, nx, nb;  // model grid, sponge width
+  int pitch, xoff;     // storage row pitch and column of padded x = 0
+  int64_t plane;       // 3-D: storage elements per z-plane
+  int64_t mplane;      // model points (frame size)
+  double eta_scale;    // eta_max * dt / 2 / nb^2
+  double w[4];         // 8th-order weights of offsets 1..4
+  const double* wp;    // W' = v^2 dt^2 / h^2, storage layout
+};
+// Advance level n -> n + 1 for every shot of tab with n < nt - 1 and store
+// frame n.
+hipError_t launch_background64(const Bg64Args& a, const Bg64Shot* tab,
+                               int nshots, int n, hipStream_t st);
+
+// Float64 CG vectors (blas.hip).
+// y = (double)x
+hipError_t launch_cvt_f2d(double* y, const float* x, int64_t n,
+                          hipStream_t st);
+// y = (float)x, or with w != NULL y[i] = (float)(w[i / seg] * x[i])
+hipError_t launch_cvt_d2f(float* y, const double* x, const float* w,
+                          int64_t seg, int64_t n, hipStream_t st);
+// r = (double)d - (double)q
+hipError_t launch_sub_d(double* r, const float* d, const float* q, int64_t n,
+                        hipStream_t st);
+// y += alpha * x
+hipError_t launch_axpy_dd(double* y, const double* x, double alpha, int64_t n,
+                          hipStream_t st);
+hipError_t launch_axpy_df(double* y, const float* x, double alpha, int64_t n,
+                          hipStream_t st);
+// p = s + beta * p
+hipError_t launch_xpby_d(double* p, const double* s, double beta, int64_t n,
+                         hipStream_t st);
+// s = g - lambda * m, and out[0] = ||s||^2
+hipError_t launch_grad_norm_d(double* s, const double* g, const double* m,
+                              double lambda, int64_t n, double* partial,
+                              double* out, hipStream_t st);
+// out[0] = sum a * b (fixed order)
+hipError_t launch_dot_d(const double* a, const double* b, int64_t n,
+                        double* partial, double* out, hipStream_t st);
+// z = (double)a * b
+hipError_t launch_mul_fd(double* z, const float* a, const double* b,
+                         int64_t n, hipStream_t st);
+
 // flag[0] = 1 if any entry of x is NaN or Inf (flag must start at 0)
 hipError_t launch_nonfinite(const float* x, int64_t n, int* flag,
                             hipStream_t st);

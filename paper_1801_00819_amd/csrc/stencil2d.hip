@@ -357,14 +357,16 @@ __global__ void k_born_last(const ShotDev* tab, int nshots, float* dat,
 
 // Image = (sum over accumulators) / W' on the model region.
 __global__ void k_adj_finalize(const double* acc, int ngroups, Geo2D g,
-                               const float* wp, float* out) {
+                               const float* wp, float* out, double* out64) {
   const int64_t mplane = (int64_t)g.nz * g.nx;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < mplane;
        i += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int k = 0; k < ngroups; ++k) s += acc[(int64_t)k * mplane + i];
     const int z = (int)(i / g.nx), x = (int)(i - (int64_t)(i / g.nx) * g.nx);
-    out[i] = (float)(s / (double)wp[sidx2(g, z + g.nb, x + g.nb)]);
+    const double v = s / (double)wp[sidx2(g, z + g.nb, x + g.nb)];
+    out[i] = (float)v;
+    if (out64) out64[i] = v;
   }
 }
 
@@ -494,12 +496,12 @@ hipError_t launch_born_last(const ShotDev* tab, int nshots, int nrec_max,
 
 hipError_t launch_adj_finalize(const double* acc, int ngroups,
                                const Geo2D& g, const float* wp, float* out,
-                               hipStream_t st) {
+                               double* out64, hipStream_t st) {
   const int64_t m = (int64_t)g.nz * g.nx;
   int blocks = (int)((m + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_adj_finalize, dim3(blocks), dim3(256), 0, st, acc,
-                     ngroups, g, wp, out);
+                     ngroups, g, wp, out, out64);
   return hipGetLastError();
 }
 

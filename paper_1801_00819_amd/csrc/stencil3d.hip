@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(StepArgs a) {
 
 // Image = (sum over accumulators) / W' on the model region (3-D).
 __global__ void k_adj_finalize3(const double* acc, int ngroups, Geo3D g,
-                                const float* wp, float* out) {
+                                const float* wp, float* out, double* out64) {
   const int64_t m = (int64_t)g.nz * g.ny * g.nx;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -410,7 +410,9 @@ __global__ void k_adj_finalize3(const double* acc, int ngroups, Geo3D g,
     const int z = (int)(i / ((int64_t)g.ny * g.nx));
     const int rem = (int)(i - (int64_t)z * g.ny * g.nx);
     const int y = rem / g.nx, x = rem - (rem / g.nx) * g.nx;
-    out[i] = (float)(s / (double)wp[sidx3(g, z + g.nb, y + g.nb, x + g.nb)]);
+    const double v = s / (double)wp[sidx3(g, z + g.nb, y + g.nb, x + g.nb)];
+    out[i] = (float)v;
+    if (out64) out64[i] = v;
   }
 }
 
@@ -476,12 +478,12 @@ hipError_t launch_step3d(int variant, int mode, const StepArgs& a,
 
 hipError_t launch_adj_finalize3(const double* acc, int ngroups,
                                 const Geo3D& g, const float* wp, float* out,
-                                hipStream_t st) {
+                                double* out64, hipStream_t st) {
   const int64_t m = (int64_t)g.nz * g.ny * g.nx;
   int blocks = (int)((m + 255) / 256);
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_adj_finalize3, dim3(blocks), dim3(256), 0, st, acc,
-                     ngroups, g, wp, out);
+                     ngroups, g, wp, out, out64);
   return hipGetLastError();
 }
 

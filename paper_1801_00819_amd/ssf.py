@@ -28,6 +28,8 @@ class SsfContext:
         self.model_size = nz * nx
         self.nt = nt
         self.device = device
+        # bumped by every update and downdate (see Context.generation)
+        self.generation = 0
 
     def close(self):
         if self._h:
@@ -65,11 +67,13 @@ class SsfContext:
         p = _ptr(data, self.device, self.nt * sh.nrec)
         sh.data = p.value if p is not None else None
         self._check(L.lib().brls_ssf_update(self._h, ctypes.byref(sh)))
+        self.generation += 1
 
     update = brls_ssf_update
 
     def brls_ssf_downdate(self, id: int):
         self._check(L.lib().brls_ssf_downdate(self._h, int(id)))
+        self.generation += 1
 
     downdate = brls_ssf_downdate
 

@@ -44,6 +44,9 @@ def test_checkpointed_and_cached_backgrounds_agree():
     idx = [0, 1]
     a = open_ctx(w, q_max=2, device=True, ckpt_interval=-1)
     b = open_ctx(w, q_max=2, device=True, ckpt_interval=0)
+    # the same float32 background arithmetic in both (stored sources
+    # default to a float64 background)
+    b.set_precision(32, 64)
     _window(a, w, idx)
     _window(b, w, idx)
     m = torch.from_numpy(f32(w.m_true)).cuda()

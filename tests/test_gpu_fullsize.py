@@ -1,0 +1,137 @@
+"""The 512 x 1024 faulted workload at full size against the oracle, through
+the C ABI, in the launch configuration the benchmark times (graph mode, the
+default launch choice): the operators over the whole first window (8 shots,
+nt = 3000, 1024 receivers each) and the chain's first two windows (20 CG
+iterations each, warm-started; the paper's block-row recursion, eqs. 10-11,
+Fig. 2d).
+
+The oracle's images of the chain are stored in
+``tests/golden/faulted2d_512x1024_chain2.npz`` by
+``tests/golden/make_faulted2d_chain.py`` (hours of oracle work); the data
+both sides use are regenerated here by the same oracle calls and checked
+against the hash stored with the images.
+"""
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+from gpu_helpers import f32, open_ctx, rel, split
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 1e-5
+IMG_TOL = 1e-4
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "faulted2d_512x1024_chain2.npz")
+
+
+def _recipe():
+    spec = importlib.util.spec_from_file_location(
+        "make_faulted2d_chain",
+        os.path.join(HERE, "golden", "make_faulted2d_chain.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    """Workload, oracle problem over shots 0-11, their clean oracle data,
+    the float32 data with noise and its hash (about a minute of oracle
+    work on the host)."""
+    mk = _recipe()
+    w, prob = mk.problem()
+    print("oracle: data of shots 0-11 at full size", flush=True)
+    clean, data, digest = mk.window_inputs(prob, w.m_true.astype(np.float32))
+    return mk, w, prob, clean, data, digest
+
+
+def _bench_tuning():
+    import bench
+    return bench.DEFAULT_TUNING
+
+
+def _window_ctx(w, lam=0.0):
+    ctx = open_ctx(w, lam=lam, q_max=8)
+    ctx.set_tuning(*_bench_tuning())
+    return ctx
+
+
+@pytest.mark.timeout(900)
+def test_full_size_born_every_shot_matches_oracle(inputs):
+    """A m_true over the whole first window: each of the 8 shots' data
+    against the oracle's."""
+    mk, w, prob, clean, data, _ = inputs
+    idx = mk.WINDOWS[0]
+    print("512x1024 born, 8-shot window, graph mode, bench launch choice",
+          flush=True)
+    ctx = _window_ctx(w)
+    for i in idx:
+        s = w.shots[i]
+        ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+    got = split(w, idx, ctx.apply_born(f32(w.m_true)))
+    ctx.close()
+    errs = [rel(got[k], clean[i]) for k, i in enumerate(idx)]
+    print("born per shot: " + " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) <= OP_TOL
+
+
+@pytest.mark.timeout(900)
+def test_full_size_adjoint_of_window_matches_oracle(inputs):
+    """A^T d over the whole first window, d the observed data of all 8
+    shots (nonzero everywhere): the library's image, summed over the shot
+    groups in float64, against the oracle's 8-shot sum."""
+    mk, w, prob, clean, data, _ = inputs
+    idx = mk.WINDOWS[0]
+    print("512x1024 adjoint, 8-shot window, graph mode, bench launch choice",
+          flush=True)
+    ctx = _window_ctx(w)
+    for i in idx:
+        s = w.shots[i]
+        ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+    got = ctx.apply_adjoint(np.concatenate([data[i].ravel() for i in idx]))
+    ctx.close()
+    print("oracle: adjoint of 8 shots", flush=True)
+    want = prob.adjoint([data[i].astype(np.float64) for i in idx], idx)
+    e = rel(got, want)
+    print(f"adjoint of the window: {e:.2e}")
+    assert e <= OP_TOL
+
+
+@pytest.mark.timeout(900)
+def test_full_size_chain_matches_oracle(inputs):
+    """The chain's first windows (8 shots sliding by 4, 20 iterations each,
+    the second warm-started from the first's image) against the oracle's
+    stored images: relative L2 <= 1e-4 per window."""
+    if not os.path.exists(GOLDEN):
+        pytest.skip("oracle images not generated "
+                    "(tests/golden/make_faulted2d_chain.py)")
+    mk, w, prob, clean, data, digest = inputs
+    g = np.load(GOLDEN, allow_pickle=False)
+    assert str(g["data_sha256"]) == digest, \
+        "regenerated data differ from the ones the oracle images used"
+    lam = float(g["lam"])
+    images = g["images"]
+    ctx = _window_ctx(w, lam)
+    held = []
+    errs = []
+    for k in range(images.shape[0]):
+        win = mk.WINDOWS[k]
+        for i in list(held):
+            if i not in win:
+                ctx.downdate(i)
+                held.remove(i)
+        for i in win:
+            if i not in held:
+                s = w.shots[i]
+                ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+                held.append(i)
+        st = ctx.solve_window(mk.NITER)
+        assert st["iters"] == mk.NITER
+        errs.append(rel(ctx.image(), images[k]))
+        print(f"window {k}: image vs oracle {errs[-1]:.2e}, ||s|| "
+              f"{st['s0_norm']:.4e} -> {st['s_norm']:.4e}", flush=True)
+    ctx.close()
+    assert max(errs) <= IMG_TOL
