@@ -247,6 +247,19 @@ int brls_apply_born(brls_ctx* ctx, const float* m, float* d_out);
  * in window order). */
 int brls_apply_adjoint(brls_ctx* ctx, const float* d, float* m_out);
 
+/* brls_apply_adjoint for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result, with the adjoint's float64 image
+ * accumulators held in a static device array of 16 MiB per device instead
+ * of the context's; it calls no hipMalloc, hipFree or other allocating
+ * routine (the context's buffers were allocated by brls_open). Runs the
+ * batched launches whatever brls_set_exec chose. The accumulators need
+ * ceil(window shots / adjoint shots per work item) * nz * ny * nx doubles;
+ * a window needing more than 16 MiB gets BRLS_EINVAL. Every call on a GPU
+ * shares that GPU's array (zeroed at the start of each call): calls that
+ * overlap on one GPU, from any context or stream, race. */
+int brls_apply_adjoint_static(brls_ctx* ctx, const float* d, float* m_out);
+
 /* Finite-difference modelling in the context's own velocity (the kind of
  * data the paper's examples migrate: finite-difference shot gathers of a
  * Ricker source, Examples section): every window shot's background

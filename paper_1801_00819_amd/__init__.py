@@ -296,6 +296,19 @@ class Context:
 
     apply_adjoint = brls_apply_adjoint
 
+    def brls_apply_adjoint_static(self, d, out=None):
+        """brls_apply_adjoint with the image accumulators in the library's
+        static device scratch (no device allocation in the call)."""
+        if not self.device:
+            d = np.ascontiguousarray(d, dtype=np.float32)
+        out = self._model_out(out)
+        self._check(L.lib().brls_apply_adjoint_static(
+            self._h, _ptr(d, self.device, self.window_data_size()),
+            _ptr(out, self.device, self.model_size)))
+        return out
+
+    apply_adjoint_static = brls_apply_adjoint_static
+
     def brls_background_window(self, out=None):
         """Finite-difference modelling in the context's velocity: each
         window shot's background wavefield at its receivers, [nt][nrec] per

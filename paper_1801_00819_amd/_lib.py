@@ -116,6 +116,7 @@ SIGNATURES = [
     ("brls_illumination", _I32, [_VP, _VP]),
     ("brls_apply_born", _I32, [_VP, _VP, _VP]),
     ("brls_apply_adjoint", _I32, [_VP, _VP, _VP]),
+    ("brls_apply_adjoint_static", _I32, [_VP, _VP, _VP]),
     ("brls_background_window", _I32, [_VP, _VP]),
     ("brls_set_exec", _I32, [_VP, _I32]),
     ("brls_set_tile", _I32, [_VP, _I32]),

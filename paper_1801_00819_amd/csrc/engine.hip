@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -43,6 +44,35 @@ constexpr double kCfl3D = 0.4529;
 constexpr int kZChunk = 32;
 
 thread_local std::string g_open_error;
+
+// Device scratch of brls_apply_adjoint_static, which allocates nothing: the
+// adjoint's float64 image accumulators, [groups][model]. Each device the
+// library runs on holds its own copy until the process ends. Host code
+// reaches it only through the per-device address from hipGetSymbolAddress
+// (scratch_dev), never through the symbol itself.
+constexpr int64_t kScratchBytes = (int64_t)16 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / 8];
+constexpr int kMaxDevices = 64;
+double* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Address of the current device's copy of `scratch`, looked up once per
+// device (brls_open). Null when the lookup failed.
+double* scratch_dev(int dev, hipError_t* err) {
+  *err = hipSuccess;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_dev[dev];
+}
 
 struct Slot {
   bool used = false;
@@ -617,11 +647,11 @@ int enqueue_born(brls_ctx* c, int batched) {
 // Two-step variants take levels k and k - 1 per launch, the field sets
 // alternating.
 int adjoint_steps(brls_ctx* c, const ShotDev* tab, int nsh, int pb, int k_hi,
-                  int k_lo, int d2_n0) {
+                  int k_lo, int d2_n0, double* acc) {
   const int dk = two_step(c) ? 2 : 1;
   int rc;
   for (int k = k_hi, i = 0; k >= k_lo; k -= dk, ++i)
-    if ((rc = step(c, kAdjoint, k, tab, nsh, pb, nullptr, c->dscr, c->acc,
+    if ((rc = step(c, kAdjoint, k, tab, nsh, pb, nullptr, c->dscr, acc,
                    d2_n0, 0, std::min(dk, k - k_lo + 1), i & 1)))
       return rc;
   return BRLS_OK;
@@ -631,7 +661,7 @@ int adjoint_steps(brls_ctx* c, const ShotDev* tab, int nsh, int pb, int k_hi,
 // the segment start, recompute the segment's Born-source frames, then run
 // the adjoint steps that consume them.
 int adjoint_segments(brls_ctx* c, const ShotDev* tab, int nsh, int pb,
-                     int nt) {
+                     int nt, double* acc) {
   int rc;
   for (int seg = nseg_of(c, nt) - 1; seg >= 0; --seg) {
     const int n0 = seg * c->ckpt_k;
@@ -641,7 +671,8 @@ int adjoint_segments(brls_ctx* c, const ShotDev* tab, int nsh, int pb,
       if ((rc = step(c, kBackground, n, tab, nsh, pb, nullptr, nullptr,
                      nullptr, n0, 1)))
         return rc;
-    if ((rc = adjoint_steps(c, tab, nsh, pb, n1, n0 + 1, n0))) return rc;
+    if ((rc = adjoint_steps(c, tab, nsh, pb, n1, n0 + 1, n0, acc)))
+      return rc;
   }
   return BRLS_OK;
 }
@@ -655,30 +686,41 @@ int adj_pb(const brls_ctx* c, int nsh) {
   return std::min(pb, nsh);
 }
 
-int enqueue_adjoint(brls_ctx* c, int batched) {
+// Float64 image accumulators of the adjoint: [groups][model]. The adjoint
+// launches of a window use ceil(shots / shots-per-item) groups.
+int64_t adjoint_acc_doubles(const brls_ctx* c, int batched) {
+  const int nsh = (int)c->order.size();
+  const int pb = batched ? adj_pb(c, nsh) : 1;
+  const int ngroups = batched ? (nsh + pb - 1) / pb : 1;
+  return (int64_t)ngroups * c->mplane;
+}
+
+int enqueue_adjoint(brls_ctx* c, int batched, double* acc) {
   const int nsh = (int)c->order.size();
   const int ntm = nt_max_of(c, c->order);
   const int pb = batched ? adj_pb(c, nsh) : 1;
   const int ngroups = batched ? (nsh + pb - 1) / pb : 1;
   int rc;
   if ((rc = zero_fields(c))) return rc;
-  HIPCHECK(c, launch_fill_f64(c->acc, ngroups * c->mplane, 0.0, c->st));
+  HIPCHECK(c, launch_fill_f64(acc, ngroups * c->mplane, 0.0, c->st));
   if (!batched) {
     for (int k = 0; k < nsh; ++k) {
       const int nt = nt_max_of(c, {c->order[k]});
-      rc = c->ckpt_k ? adjoint_segments(c, c->tab_dev + k, 1, 1, nt)
-                     : adjoint_steps(c, c->tab_dev + k, 1, 1, nt - 1, 1, 0);
+      rc = c->ckpt_k
+               ? adjoint_segments(c, c->tab_dev + k, 1, 1, nt, acc)
+               : adjoint_steps(c, c->tab_dev + k, 1, 1, nt - 1, 1, 0, acc);
       if (rc) return rc;
     }
   } else {
-    rc = c->ckpt_k ? adjoint_segments(c, c->tab_dev, nsh, pb, ntm)
-                   : adjoint_steps(c, c->tab_dev, nsh, pb, ntm - 1, 1, 0);
+    rc = c->ckpt_k
+             ? adjoint_segments(c, c->tab_dev, nsh, pb, ntm, acc)
+             : adjoint_steps(c, c->tab_dev, nsh, pb, ntm - 1, 1, 0, acc);
     if (rc) return rc;
   }
   HIPCHECK(c, c->ndim == 3
-                  ? launch_adj_finalize3(c->acc, ngroups, c->geo3, c->wp,
+                  ? launch_adj_finalize3(acc, ngroups, c->geo3, c->wp,
                                          c->gbuf, c->g64, c->st)
-                  : launch_adj_finalize(c->acc, ngroups, c->geo, c->wp,
+                  : launch_adj_finalize(acc, ngroups, c->geo, c->wp,
                                         c->gbuf, c->g64, c->st));
   return BRLS_OK;
 }
@@ -690,8 +732,9 @@ int run_op(brls_ctx* c, int op) {
     return rc;
   if (c->order.empty()) return BRLS_OK;
   if (c->exec != BRLS_EXEC_GRAPH)
-    return op == kBorn ? enqueue_born(c, c->exec == BRLS_EXEC_BATCHED)
-                       : enqueue_adjoint(c, c->exec == BRLS_EXEC_BATCHED);
+    return op == kBorn
+               ? enqueue_born(c, c->exec == BRLS_EXEC_BATCHED)
+               : enqueue_adjoint(c, c->exec == BRLS_EXEC_BATCHED, c->acc);
   const int nsh = (int)c->order.size();
   const bool adj = op == kAdjoint;
   const GraphKey key(op, nsh,
@@ -703,7 +746,7 @@ int run_op(brls_ctx* c, int op) {
     const bool was_timing = c->timing;
     c->timing = false;
     HIPCHECK(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-    rc = op == kBorn ? enqueue_born(c, 1) : enqueue_adjoint(c, 1);
+    rc = op == kBorn ? enqueue_born(c, 1) : enqueue_adjoint(c, 1, c->acc);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(c->st, &graph);
     c->timing = was_timing;
@@ -841,6 +884,16 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
     c->own_stream = true;
   }
   c->device = dev;
+  {
+    hipError_t e = hipSuccess;
+    if (!scratch_dev(dev, &e)) {
+      if (c->own_stream) (void)hipStreamDestroy(c->st);
+      delete c;
+      return fail(nullptr, BRLS_EDEVICE,
+                  "hipGetSymbolAddress of the static scratch: %s",
+                  hipGetErrorString(e));
+    }
+  }
   c->ndim = g.ndim;
   const double eta_max = 3.0 * vmax * std::log(1000.0) / (2.0 * g.nb * g.h);
   c->eta_scale64 = eta_max * g.dt / 2.0 / ((double)g.nb * g.nb);
@@ -1606,6 +1659,51 @@ int brls_apply_adjoint(brls_ctx* c, const float* d, float* m_out) {
   return BRLS_OK;
 }
 
+int brls_apply_adjoint_static(brls_ctx* c, const float* d, float* m_out) {
+  if (!c || !d || !m_out) return fail(c, BRLS_EINVAL, "NULL argument");
+  hipError_t e = hipSuccess;
+  double* acc = scratch_dev(c->device, &e);
+  if (!acc)
+    return fail(c, BRLS_EDEVICE, "static scratch unavailable: %s",
+                hipGetErrorString(e));
+  const int64_t need = adjoint_acc_doubles(c, 1);
+  if (need * 8 > kScratchBytes)
+    return fail(c, BRLS_EINVAL,
+                "the window's image accumulators need %lld bytes; the static "
+                "scratch holds %lld (fewer shots per window, more shots per "
+                "adjoint work item, or brls_apply_adjoint)",
+                (long long)(need * 8), (long long)kScratchBytes);
+  int rc;
+  if ((rc = ensure_tab(c)) || (rc = ensure_backgrounds(c)) ||
+      (rc = ensure_tab(c)))
+    return rc;
+  HIPCHECK(c, launch_fill_f32(c->dscr, (int64_t)c->g.q_max * c->seg, 0.f,
+                              c->st));
+  int64_t off = 0;
+  for (int i : c->order) {
+    const Slot& sl = c->slots[i];
+    const int64_t nd = (int64_t)sl.nt * sl.nrec;
+    HIPCHECK(c, hipMemcpyAsync(c->dscr + sl.dat_off, d + off, nd * 4,
+                               in_kind(c), c->st));
+    off += nd;
+  }
+  if (c->order.empty()) {
+    HIPCHECK(c, launch_fill_f32(c->gbuf, c->mplane, 0.f, c->st));
+  } else {
+    // batched launches, no graph (instantiating one may allocate) and no
+    // per-launch timing events
+    const bool was_timing = c->timing;
+    c->timing = false;
+    rc = enqueue_adjoint(c, 1, acc);
+    c->timing = was_timing;
+    if (rc) return rc;
+  }
+  HIPCHECK(c, hipMemcpyAsync(m_out, c->gbuf, c->mplane * 4, out_kind(c),
+                             c->st));
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  return BRLS_OK;
+}
+
 int brls_set_exec(brls_ctx* c, int32_t mode) {
   if (!c) return BRLS_EINVAL;
   if (mode < BRLS_EXEC_PLAIN || mode > BRLS_EXEC_GRAPH)
@@ -1713,7 +1811,8 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
   // time one operator application with the current settings
   auto timed = [&](int op, float* ms) -> int {
     HIPCHECK(c, hipEventRecord(e0, c->st));
-    const int r = op == kBorn ? enqueue_born(c, 1) : enqueue_adjoint(c, 1);
+    const int r =
+        op == kBorn ? enqueue_born(c, 1) : enqueue_adjoint(c, 1, c->acc);
     if (r) return r;
     HIPCHECK(c, hipEventRecord(e1, c->st));
     HIPCHECK(c, hipEventSynchronize(e1));
