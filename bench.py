@@ -176,6 +176,17 @@ def algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec, steps=1):
     return Q * per_shot + ngroups * shared
 
 
+def point_step_bytes(kind, B):
+    """Algorithmic float32 bytes per (padded point, time step, shot) of one
+    operator with stored Born sources, B shots sharing a work item, as a
+    one-step-per-launch kernel moves them: the propagated field's u and v
+    each read and written (16 B), plus per work item the medium W' (4 B)
+    and, for Born, the model vector (4 B): Born 16 + 8 / B, adjoint
+    16 + 4 / B (the image accumulator held on chip; the Born-source frame
+    counted in neither, as in the per-step count of the design)."""
+    return 16.0 + (8.0 if kind == "born" else 4.0) / B
+
+
 def fixed_residual(args, P, w, data, lam, vel, torch):
     """Seconds per window solve at a fixed CG residual. The stop test is
     ||A^T r - lambda m|| <= tau ||A^T d||, with tau the ratio the first
@@ -1185,9 +1196,12 @@ def main():
         avg_s = ms / n / 1e3
         pb = tuning["born_per_block" if kind == "born" else "adj_per_block"]
         ngroups = (Q + pb - 1) // pb
-        byt = algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec, steps)
-        roof[kind] = dict(avg_us=avg_s * 1e6, bytes=byt,
-                          gbs=byt / avg_s / 1e9)
+        units = Q * npad * steps  # padded point-steps of one launch
+        byt = int(round(point_step_bytes(kind, pb) * units))
+        least = algorithmic_bytes(kind, Q, ngroups, npad, nint, nrec, steps)
+        roof[kind] = dict(avg_us=avg_s * 1e6, bytes=byt, units=units,
+                          gbs=byt / avg_s / 1e9, least=least,
+                          least_gbs=least / avg_s / 1e9)
     dom = max(roof, key=lambda k: roof[k]["avg_us"])
     r = roof[dom]
     kname = KERNEL_NAME[P.tile_variants()[var][3]]
@@ -1211,8 +1225,16 @@ def main():
                         if traffic else None),
         "avg_launch_us": round(r["avg_us"], 2),
         "algorithmic_bytes_per_launch": r["bytes"],
+        "bytes_basis": f"{point_step_bytes(dom, pb_dom):g} B per padded "
+                       f"point, step and shot x {r['units']} point-step-"
+                       "shots per launch",
+        # what a launch must move at minimum when it takes `steps` steps
+        # (fields read and written once per launch): the tighter count
+        "least_bytes_per_launch": r["least"],
+        "least_frac": round(r["least_gbs"] / HBM_PEAK_GBS, 4),
         "other": {k: {"avg_launch_us": round(v["avg_us"], 2),
-                      "achieved_GBs": round(v["gbs"], 1)}
+                      "achieved_GBs": round(v["gbs"], 1),
+                      "frac": round(v["gbs"] / HBM_PEAK_GBS, 4)}
                   for k, v in roof.items() if k != dom},
     }
     log(f"roofline: {roof}")

@@ -108,7 +108,11 @@ typedef struct {
   double total_ms; /* summed durations between events bracketing each launch */
 } brls_kstat;
 
-/* Create a context for one velocity model.
+/* Create a context for one velocity model: the background medium in which
+ * eq. 1's de-migration operator A and eq. 2's migration operator A^T are
+ * linearised (Least squares migration section), the damping lambda of
+ * eq. 3, and an empty window of at most q_max shots for the block-row
+ * recursion (eqs. 10-11), whose image starts at zero.
  * g: grid (copied). vel: host [nz][ny][nx] velocity in m/s, all > 0.
  * stream: hipStream_t to order all work on; NULL gives the context a private
  * stream that synchronises with the null stream (graphs cannot capture the
@@ -122,11 +126,16 @@ typedef struct {
 int brls_open(const brls_grid* g, const float* vel, void* stream,
               brls_ctx** out);
 
-/* Release every device and host resource of the context. NULL is a no-op. */
+/* End the recursion of eqs. 10-11 on this context: release every device
+ * and host resource (the window's data, background caches and image). NULL
+ * is a no-op. */
 void brls_close(brls_ctx* ctx);
 
 /* Message of the last failing call on ctx (or of the last failing brls_open
- * when ctx is NULL). Valid until the next call on the same context. */
+ * when ctx is NULL). Valid until the next call on the same context. The
+ * failures it explains are those of the calls above: invalid windows or
+ * shots (the update and downdate after eq. 10), breakdown or non-finite
+ * scalars of the window CG (eq. 10), device errors. */
 const char* brls_last_error(const brls_ctx* ctx);
 
 /* Rank-one part of the paper's rank-K update (after eq. 10, Fig. 1): add one

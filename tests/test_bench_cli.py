@@ -38,3 +38,19 @@ def test_adjoint_algorithmic_bytes_of_the_headline_launch():
     born = 8 * per_shot + 8 * (4 * npad + 4 * nint)
     assert bench.algorithmic_bytes("born", 8, 8, npad, nint, nrec,
                                    steps=2) == born
+
+
+def test_point_step_bytes_of_the_headline_launches():
+    """The roofline's byte basis: per padded point, time step and shot,
+    Born 16 + 8/B and adjoint 16 + 4/B bytes; one two-step launch over the
+    8-shot window of the 592 x 1104 padded grid is 10 457 088 point-steps,
+    i.e. 177.8 MB for the adjoint in groups of 4 shots and 251.0 MB for
+    Born with one shot per work item."""
+    sys.path.insert(0, ROOT)
+    import bench
+    units = 8 * 592 * 1104 * 2
+    assert units == 10457088
+    assert bench.point_step_bytes("adjoint", 4) == 17.0
+    assert bench.point_step_bytes("born", 1) == 24.0
+    assert round(bench.point_step_bytes("adjoint", 4) * units) == 177770496
+    assert round(bench.point_step_bytes("born", 1) * units) == 250970112
