@@ -37,16 +37,18 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # launch choice used unless --autotune is given (and by the counter runs):
 # tile variant, Born shots per block and grid shape, adjoint shots per block
 # and grid shape -- the fastest in a sweep of all choices on this workload
-# (z-marching wavefronts taking two time steps per launch over 16-row
-# chunks; Born one shot per work item; adjoint in cooperative blocks of four
-# wavefronts, one shot each, summing their image contributions in LDS, on a
-# grid of resident blocks)
-DEFAULT_TUNING = (18, 1, 0, 4, 1)
+# (segment-marching wavefronts taking two time steps per launch over
+# 16-row segments, blocks of four wavefronts marching the four shots of a
+# group on one segment -- the adjoint's summing their image contributions
+# in LDS -- on a grid of resident blocks whose work items run strips
+# fastest)
+DEFAULT_TUNING = (24, 4, 5, 4, 5)
 # with checkpointed backgrounds (no stored Born sources): the fastest
 # one-step choice
 DEFAULT_TUNING_CKPT = (16, 1, 0, 4, 2)
 # kernel behind each tile kind (the fourth number of a tile variant)
-KERNEL_NAME = {0: "k_step2d", 1: "k_step2d", 2: "k_march2d", 3: "k_march2t"}
+KERNEL_NAME = {0: "k_step2d", 1: "k_step2d", 2: "k_march2d", 3: "k_march2t",
+               4: "k_march2s"}
 DEFAULT_TILE3 = 0
 
 # HBM bytes per launch of the 2-D step kernel under DEFAULT_TUNING, from
@@ -1189,7 +1191,7 @@ def main():
     ks = ctx.kernel_stats()
     ctx.kernel_timing(False)
     var = tuning["variant"]
-    steps = 2 if P.tile_variants()[var][3] == 3 else 1  # steps per launch
+    steps = 2 if P.tile_variants()[var][3] >= 3 else 1  # steps per launch
     roof = {}
     for kind, name in (("born", "born_step"), ("adjoint", "adjoint_step")):
         n, ms = ks[name]

@@ -62,6 +62,10 @@ extern "C" {
 #define BRLS_EXEC_PLAIN 0   /* one kernel launch per shot and per time step */
 #define BRLS_EXEC_BATCHED 1 /* one launch per time step for all window shots */
 #define BRLS_EXEC_GRAPH 2   /* batched; the time loop is replayed as a hipGraph */
+#define BRLS_EXEC_PERSISTENT 3 /* one launch per operator application: a
+                                  resident grid runs every time step, with
+                                  a grid barrier between two-step levels
+                                  (replayed as a hipGraph) */
 
 typedef struct brls_ctx brls_ctx;
 
@@ -280,8 +284,21 @@ int brls_apply_adjoint_static(brls_ctx* ctx, const float* d, float* m_out);
 int brls_background_window(brls_ctx* ctx, float* out);
 
 /* Execution mode for the operator pair (BRLS_EXEC_*). Results agree across
- * modes to rounding of the image reduction order. */
+ * modes to rounding of the image reduction order. BRLS_EXEC_PERSISTENT
+ * needs a 2-D context with stored Born sources and a tile variant of kind
+ * 4 (BRLS_EINVAL otherwise): each Born or adjoint application is one
+ * launch of at most as many blocks as the device holds at once, which
+ * runs all time steps, every block waiting at a grid barrier between
+ * consecutive two-step levels (all the window's shots and time steps in
+ * one launch, as a batching form of the method's operators, eqs. 1-2 per
+ * window, eq. 10). */
 int brls_set_exec(brls_ctx* ctx, int32_t mode);
+
+/* Bound of the persistent kernel's barrier waits, in polls (default 2^20,
+ * about a second). A wait that reaches it gives up: the launch ends, the
+ * operator call returns BRLS_EDEVICE and its result is invalid; no launch
+ * can hang. Tests set 0 to force that path. */
+int brls_set_spin_limit(brls_ctx* ctx, int32_t polls);
 
 /* Tile shape of the stencil kernels: index into the compiled variants
  * (brls_tile_count); -1 restores the default. brls_tile_info reports a
@@ -290,7 +307,11 @@ int brls_set_exec(brls_ctx* ctx, int32_t mode);
  * runs its shots in turn; 1 = the same, the next shot's loads issued before
  * the current shot is computed; 2 = z-marching wavefronts: each wavefront
  * walks a tx-column strip down a tz-row chunk with the z-stencil in
- * registers and the x-stencil from neighbouring lanes (thread rows 1). */
+ * registers and the x-stencil from neighbouring lanes (thread rows 1);
+ * 3 = the same taking two time steps per launch; 4 = two steps per launch,
+ * each wavefront marching a segment of tz rows for one shot with the rows
+ * shared by consecutive chunks kept in registers, a block holding the
+ * wavefronts of one shot group (needed by BRLS_EXEC_PERSISTENT). */
 int brls_set_tile(brls_ctx* ctx, int32_t variant);
 int brls_tile_count(int32_t* n);
 /* 3-D variants: XY tile tx x ty and the shots a block advances together
@@ -316,18 +337,26 @@ int brls_get_resident_grid(const brls_ctx* ctx, int32_t* enable);
  * shape of the Born (and background) launches and of the adjoint launches.
  * Grid shape bits: bit 0 = resident grid (as brls_set_resident_grid);
  * bit 1 (2-D only) = work items dealt to blocks in launch order instead of
- * in 8 contiguous ranges, one per XCD. 3-D variants fix the shots per
- * block. */
+ * in 8 contiguous ranges, one per XCD; bit 2 (2-D two-step variants) =
+ * strips vary fastest along the work items (wavefronts that run together
+ * cover whole grid rows) instead of chunks of one strip. 3-D variants fix
+ * the shots per block. */
 int brls_set_tuning(brls_ctx* ctx, int32_t variant, int32_t born_pb,
                     int32_t born_grid, int32_t adj_pb, int32_t adj_grid);
 int brls_get_tuning(const brls_ctx* ctx, int32_t* variant, int32_t* born_pb,
                     int32_t* born_grid, int32_t* adj_pb, int32_t* adj_grid);
 
-/* Time every tile variant, shots-per-block choice and grid shape on the
- * current window
+/* 3-D only: z planes per work item of the 3-D kernels (default 32; 1 ..
+ * 4096). Errors: BRLS_EINVAL (2-D context or out of range). */
+int brls_set_zchunk(brls_ctx* ctx, int32_t planes);
+int brls_get_zchunk(const brls_ctx* ctx, int32_t* planes);
+
+/* Time every tile variant, shots-per-block choice and grid shape (3-D:
+ * also z planes per work item 8, 16, 32, 64) on the current window
  * (Born and adjoint applications of 400 time steps, results discarded)
  * and keep the fastest, shots per block and grid shape chosen per operator.
- * Returns the chosen variant in *best. */
+ * Returns the chosen variant in *best. In persistent execution only the
+ * variants that support it are tried. */
 int brls_autotune(brls_ctx* ctx, int32_t* best);
 
 /* Per-kernel timing with HIP events around every launch (adds small gaps

@@ -22,11 +22,11 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (BRLS_EXEC_BATCHED, BRLS_EXEC_GRAPH,  # noqa: F401
-                   BRLS_EXEC_PLAIN, BrlsError)
+                   BRLS_EXEC_PERSISTENT, BRLS_EXEC_PLAIN, BrlsError)
 
 __all__ = [
     "Context", "brls_open", "BrlsError", "BRLS_EXEC_PLAIN",
-    "BRLS_EXEC_BATCHED", "BRLS_EXEC_GRAPH",
+    "BRLS_EXEC_BATCHED", "BRLS_EXEC_GRAPH", "BRLS_EXEC_PERSISTENT",
 ]
 
 
@@ -330,6 +330,25 @@ class Context:
         self._check(L.lib().brls_set_exec(self._h, int(mode)))
 
     set_exec = brls_set_exec
+
+    def brls_set_spin_limit(self, polls: int):
+        """Polls before a persistent launch's barrier wait gives up."""
+        self._check(L.lib().brls_set_spin_limit(self._h, int(polls)))
+
+    set_spin_limit = brls_set_spin_limit
+
+    def brls_set_zchunk(self, planes: int):
+        """3-D: z planes per work item of the 3-D kernels."""
+        self._check(L.lib().brls_set_zchunk(self._h, int(planes)))
+
+    set_zchunk = brls_set_zchunk
+
+    def brls_get_zchunk(self) -> int:
+        v = ctypes.c_int32()
+        self._check(L.lib().brls_get_zchunk(self._h, ctypes.byref(v)))
+        return v.value
+
+    get_zchunk = brls_get_zchunk
 
     def brls_set_tile(self, variant: int, shots_per_block: Optional[int] = None):
         self._check(L.lib().brls_set_tile(self._h, int(variant)))

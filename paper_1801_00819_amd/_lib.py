@@ -27,6 +27,7 @@ BRLS_DEVICE_PTRS = 1
 BRLS_EXEC_PLAIN = 0
 BRLS_EXEC_BATCHED = 1
 BRLS_EXEC_GRAPH = 2
+BRLS_EXEC_PERSISTENT = 3
 
 ERROR_NAMES = {
     BRLS_EINVAL: "EINVAL", BRLS_ENOMEM: "ENOMEM", BRLS_EFULL: "EFULL",
@@ -119,6 +120,9 @@ SIGNATURES = [
     ("brls_apply_adjoint_static", _I32, [_VP, _VP, _VP]),
     ("brls_background_window", _I32, [_VP, _VP]),
     ("brls_set_exec", _I32, [_VP, _I32]),
+    ("brls_set_spin_limit", _I32, [_VP, _I32]),
+    ("brls_set_zchunk", _I32, [_VP, _I32]),
+    ("brls_get_zchunk", _I32, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     ("brls_set_tile", _I32, [_VP, _I32]),
     ("brls_tile_count", _I32, [ctypes.POINTER(_I32)]),
     ("brls_tile_info", _I32, [_I32, ctypes.POINTER(_I32),

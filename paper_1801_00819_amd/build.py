@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbrrlsm.so")
 SOURCES = ["stencil2d.hip", "march2d.hip", "march2t.hip", "stencil3d.hip",
-           "bg64.hip",
+           "march2s.hip", "bg64.hip",
            "blas.hip", "engine.hip", "ssf.hip", "ssf_engine.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

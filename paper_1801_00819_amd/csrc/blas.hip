@@ -18,6 +18,12 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
     p[i] = v;
 }
 
+__global__ void k_fill_u32(unsigned* p, int64_t n, unsigned v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void k_fill_f64(double* p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -215,6 +221,13 @@ static int grid_for(int64_t n) {
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -40,8 +40,6 @@ constexpr double kW1 = 8.0 / 5.0, kW2 = -1.0 / 5.0, kW3 = 8.0 / 315.0,
 constexpr double kCfl2D = 0.5546;
 // Same for 3-D: C <= 2 / sqrt(3 S).
 constexpr double kCfl3D = 0.4529;
-// z planes per 3-D work item
-constexpr int kZChunk = 32;
 
 thread_local std::string g_open_error;
 
@@ -110,8 +108,9 @@ const char* kTimerNames[kTNumKinds] = {"background_step", "born_step",
                                        "adjoint_step", "born_graph",
                                        "adjoint_graph"};
 
-// op, shots, shots per block, tile variant, time steps, resident grid
-using GraphKey = std::tuple<int, int, int, int, int, int>;
+// op, shots, shots per block, tile variant, time steps, resident grid,
+// execution mode
+using GraphKey = std::tuple<int, int, int, int, int, int, int>;
 
 }  // namespace
 
@@ -129,6 +128,7 @@ struct brls_ctx {
   int adj_per_block = 4;  // adjoint launches
   int adj_resident_grid = 0;
   int tune_nt = 0;      // > 0 while autotuning: time steps per trial
+  int zchunk = 32;      // 3-D: z planes per work item
   int exec = BRLS_EXEC_GRAPH;
   int rows_alloc = 0;
   int64_t fs = 0;      // floats per field buffer
@@ -147,6 +147,10 @@ struct brls_ctx {
                           // the image the solve starts from
   float* dm = nullptr;    // that correction (mode 1)
   double* acc = nullptr;
+  // persistent execution: grid barrier arrivals and failure flag
+  unsigned* pcounter = nullptr;
+  int* perror = nullptr;
+  int spin_limit = 1 << 20;  // barrier polls before a wait gives up
   // precision (brls_set_precision): float64 background of new shots (stored
   // Born sources only) and float64 CG vectors
   int bg64 = 1;
@@ -243,7 +247,7 @@ void set_variant_geo(brls_ctx* c, int v) {
     Geo3D& g = c->geo3;
     g.ntx = (g.px - g.x_org + ts.tx - 1) / ts.tx;
     g.nty = (g.py + ts.ty - 1) / ts.ty;
-    g.tzc = kZChunk;
+    g.tzc = c->zchunk;
     g.ntz = (g.pz + g.tzc - 1) / g.tzc;
     g.ntiles = g.ntx * g.nty * g.ntz;
   } else {
@@ -287,7 +291,7 @@ int build_receiver_tiles(brls_ctx* c, Slot& sl) {
     const TileShape ts = tile_shape(c->variant);
     const Geo2D& g = c->geo;
     const int pz = sl.rec[3 * j] + g.nb, px = sl.rec[3 * j + 2] + g.nb;
-    if (ts.pipe != 3) {
+    if (ts.pipe < 3) {
       const int tzi = pz / ts.tz, txi = (px - g.x_org) / ts.tx;
       ms.push_back({tzi * g.ntx + txi,
                     (pz - tzi * ts.tz) * ts.tx + (px - g.x_org - txi * ts.tx),
@@ -414,9 +418,15 @@ StepArgs base_args(const brls_ctx* c) {
   return a;
 }
 
+// The persistent form runs the segment-marching two-step kernel (tile kind
+// 4), which needs stored Born sources.
+bool persistent_ok(const brls_ctx* c, int variant) {
+  return c->ndim == 2 && !c->ckpt_k && tile_shape(variant).pipe == 4;
+}
+
 // Whether the 2-D tile variant advances two time steps per launch.
 bool two_step(const brls_ctx* c) {
-  return c->ndim == 2 && tile_shape(c->variant).pipe == 3;
+  return c->ndim == 2 && tile_shape(c->variant).pipe >= 3;
 }
 
 // One time step over `nshots` table entries starting at `tab` (two-step
@@ -621,6 +631,28 @@ int enqueue_born(brls_ctx* c, int batched) {
   if ((rc = zero_fields(c))) return rc;
   // one step per launch, or two (levels n, n + 1; the field sets alternate)
   const int dn = two_step(c) ? 2 : 1;
+  if (batched && c->exec == BRLS_EXEC_PERSISTENT) {
+    // one launch for all two-step launches of the application
+    StepArgs a = base_args(c);
+    a.tab = c->tab_dev;
+    a.nshots = nsh;
+    a.per_block = std::min(c->per_block, nsh);
+    a.ngroups = (nsh + a.per_block - 1) / a.per_block;
+    a.pm = c->born_in;
+    a.dat = c->q;
+    PersistArgs p{};
+    p.counter = c->pcounter;
+    p.error = c->perror;
+    p.nlaunch = (ntm - 1 + 1) / 2;
+    p.nt_max = ntm;
+    p.spin_limit = c->spin_limit;
+    const TileShape ts = tile_shape(c->variant);
+    HIPCHECK(c, launch_fill_u32(c->pcounter, 2, 0u, c->st));
+    HIPCHECK(c, launch_march2s_persistent(ts.tz, ts.ntz, kBorn, a, p, c->st));
+    HIPCHECK(c, launch_born_last(c->tab_dev, nsh, c->g.nrec_max, c->q, 1,
+                                 c->st));
+    return BRLS_OK;
+  }
   auto run = [&](const ShotDev* tab, int ns, int pb, int nt) -> int {
     for (int n = 0, i = 0; n + 1 < nt; n += dn, ++i) {
       const int r = step(c, mode, n, tab, ns, pb, c->born_in, c->q, nullptr,
@@ -703,7 +735,27 @@ int enqueue_adjoint(brls_ctx* c, int batched, double* acc) {
   int rc;
   if ((rc = zero_fields(c))) return rc;
   HIPCHECK(c, launch_fill_f64(acc, ngroups * c->mplane, 0.0, c->st));
-  if (!batched) {
+  if (batched && c->exec == BRLS_EXEC_PERSISTENT) {
+    StepArgs a = base_args(c);
+    a.resident_grid = c->adj_resident_grid;
+    a.tab = c->tab_dev;
+    a.nshots = nsh;
+    a.per_block = pb;
+    a.ngroups = ngroups;
+    a.dat = c->dscr;
+    a.acc = acc;
+    PersistArgs p{};
+    p.counter = c->pcounter;
+    p.error = c->perror;
+    p.k_hi = ntm - 1;
+    p.k_lo = 1;
+    p.nlaunch = (ntm - 1 + 1) / 2;
+    p.spin_limit = c->spin_limit;
+    const TileShape ts = tile_shape(c->variant);
+    HIPCHECK(c, launch_fill_u32(c->pcounter, 2, 0u, c->st));
+    HIPCHECK(c, launch_march2s_persistent(ts.tz, ts.ntz, kAdjoint, a, p,
+                                          c->st));
+  } else if (!batched) {
     for (int k = 0; k < nsh; ++k) {
       const int nt = nt_max_of(c, {c->order[k]});
       rc = c->ckpt_k
@@ -731,7 +783,7 @@ int run_op(brls_ctx* c, int op) {
       (rc = ensure_tab(c)))
     return rc;
   if (c->order.empty()) return BRLS_OK;
-  if (c->exec != BRLS_EXEC_GRAPH)
+  if (c->exec != BRLS_EXEC_GRAPH && c->exec != BRLS_EXEC_PERSISTENT)
     return op == kBorn
                ? enqueue_born(c, c->exec == BRLS_EXEC_BATCHED)
                : enqueue_adjoint(c, c->exec == BRLS_EXEC_BATCHED, c->acc);
@@ -740,7 +792,7 @@ int run_op(brls_ctx* c, int op) {
   const GraphKey key(op, nsh,
                      adj ? adj_pb(c, nsh) : std::min(c->per_block, nsh),
                      c->variant, nt_max_of(c, c->order),
-                     adj ? c->adj_resident_grid : c->resident_grid);
+                     adj ? c->adj_resident_grid : c->resident_grid, c->exec);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     const bool was_timing = c->timing;
@@ -765,7 +817,19 @@ int run_op(brls_ctx* c, int op) {
   if ((rc = timed_begin(c, op == kBorn ? kTBornGraph : kTAdjGraph, &t)))
     return rc;
   HIPCHECK(c, hipGraphLaunch(it->second.second, c->st));
-  return timed_end(c, &t);
+  if ((rc = timed_end(c, &t))) return rc;
+  if (c->exec == BRLS_EXEC_PERSISTENT) {
+    int bad = 0;
+    HIPCHECK(c, hipMemcpyAsync(&bad, c->perror, sizeof(int),
+                               hipMemcpyDeviceToHost, c->st));
+    HIPCHECK(c, hipStreamSynchronize(c->st));
+    if (bad)
+      return fail(c, BRLS_EDEVICE,
+                  "persistent launch: a grid barrier wait gave up after %d "
+                  "polls; the operator's result is invalid",
+                  c->spin_limit);
+  }
+  return BRLS_OK;
 }
 
 void drop_graphs(brls_ctx* c) {
@@ -1003,6 +1067,8 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
   ALLOC(c->dscr, (int64_t)g.q_max * c->seg);
   ALLOC(c->wslot, g.q_max);
   ALLOC(c->partial, kDotBlocks);
+  ALLOC(c->pcounter, 2);  // [0] arrivals, [1] the failure flag
+  c->perror = reinterpret_cast<int*>(c->pcounter + 1);
   ALLOC(c->scal, 16);
   ALLOC(c->flag, 1);
   ALLOC(c->tab_dev, g.q_max);
@@ -1706,9 +1772,42 @@ int brls_apply_adjoint_static(brls_ctx* c, const float* d, float* m_out) {
 
 int brls_set_exec(brls_ctx* c, int32_t mode) {
   if (!c) return BRLS_EINVAL;
-  if (mode < BRLS_EXEC_PLAIN || mode > BRLS_EXEC_GRAPH)
+  if (mode < BRLS_EXEC_PLAIN || mode > BRLS_EXEC_PERSISTENT)
     return fail(c, BRLS_EINVAL, "unknown exec mode %d", mode);
+  if (mode == BRLS_EXEC_PERSISTENT && !persistent_ok(c, c->variant))
+    return fail(c, BRLS_EINVAL,
+                "persistent execution needs a 2-D context with stored Born "
+                "sources and a segment-marching tile variant (kind 4); "
+                "variant %d is kind %d",
+                c->variant, tile_shape(c->variant).pipe);
   c->exec = mode;
+  return BRLS_OK;
+}
+
+int brls_set_zchunk(brls_ctx* c, int32_t planes) {
+  if (!c) return BRLS_EINVAL;
+  if (c->ndim != 3)
+    return fail(c, BRLS_EINVAL, "z chunks are a 3-D launch parameter");
+  if (planes < 1 || planes > 4096)
+    return fail(c, BRLS_EINVAL, "z chunk of %d planes out of range", planes);
+  HIPCHECK(c, hipStreamSynchronize(c->st));
+  c->zchunk = planes;
+  set_variant_geo(c, c->variant);
+  drop_graphs(c);
+  return BRLS_OK;
+}
+
+int brls_get_zchunk(const brls_ctx* c, int32_t* planes) {
+  if (!c || !planes) return BRLS_EINVAL;
+  *planes = c->zchunk;
+  return BRLS_OK;
+}
+
+int brls_set_spin_limit(brls_ctx* c, int32_t polls) {
+  if (!c) return BRLS_EINVAL;
+  if (polls < 0) return fail(c, BRLS_EINVAL, "spin limit %d < 0", polls);
+  c->spin_limit = polls;
+  drop_graphs(c);  // the limit is a kernel argument baked into graphs
   return BRLS_OK;
 }
 
@@ -1748,13 +1847,22 @@ static int set_tile_impl(brls_ctx* c, int v, int per_block,
                          int adj_per_block) {
   if (v < 0 || v >= variant_count(c))
     return fail(c, BRLS_EINVAL, "tile variant %d out of range", v);
-  if (c->ndim == 2 && c->ckpt_k && tile_shape(v).pipe == 3)
+  if (c->ndim == 2 && c->ckpt_k && tile_shape(v).pipe >= 3)
     return fail(c, BRLS_EINVAL,
                 "tile variant %d takes two steps per launch and needs stored "
                 "Born sources (checkpoint interval 0)",
                 v);
+  if (c->exec == BRLS_EXEC_PERSISTENT && !persistent_ok(c, v))
+    return fail(c, BRLS_EINVAL,
+                "tile variant %d cannot run in persistent execution (needs "
+                "kind 4)", v);
   if (per_block < 1) per_block = 1;
   if (adj_per_block < 1) adj_per_block = 1;
+  // segment-marching variants run one wavefront per shot of a block
+  if (c->ndim == 2 && tile_shape(v).pipe == 4 &&
+      (per_block > 8 || adj_per_block > 8))
+    return fail(c, BRLS_EINVAL,
+                "tile variant %d runs at most 8 shots per work item", v);
   // 3-D kernels advance a fixed number of shots per block together
   if (c->ndim == 3) per_block = adj_per_block = tile_shape3(v).sb;
   HIPCHECK(c, hipStreamSynchronize(c->st));
@@ -1804,9 +1912,9 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
   const int saved_exec = c->exec;
   const int saved_v = c->variant, saved_pb = c->per_block,
             saved_apb = c->adj_per_block, saved_rg = c->resident_grid,
-            saved_arg = c->adj_resident_grid;
+            saved_arg = c->adj_resident_grid, saved_zc = c->zchunk;
   int best_v = saved_v, best_pb = saved_pb, best_apb = saved_apb,
-      best_rg = saved_rg, best_arg = saved_arg;
+      best_rg = saved_rg, best_arg = saved_arg, best_zc = saved_zc;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // time one operator application with the current settings
   auto timed = [&](int op, float* ms) -> int {
@@ -1827,23 +1935,37 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
     // not depend on the step index)
     c->tune_nt = 400;
     float best_total = 1e30f;
+    // 3-D: z planes per work item 8, 16, 32, 64; 2-D: one pass
+    const int nzc = c->ndim == 3 ? 4 : 1;
+    for (int zi = 0; zi < nzc; ++zi)
     for (int v = 0; v < variant_count(c); ++v) {
-      if (c->ndim == 2 && c->ckpt_k && tile_shape(v).pipe == 3) continue;
+      if (c->ndim == 2 && c->ckpt_k && tile_shape(v).pipe >= 3) continue;
+      if (saved_exec == BRLS_EXEC_PERSISTENT && !persistent_ok(c, v))
+        continue;
+      if (c->ndim == 3) c->zchunk = 8 << zi;
       // the tile shape fixes the receiver lists; shots per block and grid
       // shape are chosen per operator
       float bt[2] = {1e30f, 1e30f};
       int bpb[2] = {1, 1}, brg[2] = {0, 0};
       // shots per block 1, 2, 4, 8 x grid shape: one block per item,
-      // resident grid, items in launch order (2-D only)
-      for (int trial = 0; trial < 12; ++trial) {
-        int pb = 1 << (trial / 3);
-        const int rg = trial % 3;
+      // resident grid, items in launch order (2-D only); two-step 2-D
+      // variants also with strips varying fastest (bit 2)
+      const bool xf = c->ndim == 2 && tile_shape(v).pipe >= 3;
+      static const int kShapes2D[] = {0, 1, 2, 4, 5};
+      const int nshape = c->ndim == 3 ? 2 : (xf ? 5 : 3);
+      for (int trial = 0; trial < 4 * nshape; ++trial) {
+        int pb = 1 << (trial / nshape);
+        const int rg = c->ndim == 3 ? trial % nshape
+                                    : kShapes2D[trial % nshape];
         if (c->ndim == 3) {  // shots per block fixed by the variant
-          if (trial > 1) break;
+          if (trial >= nshape) break;
           pb = tile_shape3(v).sb;
         }
         if (pb > nsh && pb > 1) break;
         int r;
+        // set_tile_impl rebuilds the geometry (and the z chunk) when the
+        // variant changes; force it for a new z chunk
+        if (c->ndim == 3 && trial == 0) set_variant_geo(c, v);
         if ((r = set_tile_impl(c, v, pb, pb))) return r;
         c->resident_grid = c->adj_resident_grid = rg;
         for (int k = 0; k < 2; ++k) {
@@ -1863,6 +1985,7 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
         best_apb = bpb[1];
         best_rg = brg[0];
         best_arg = brg[1];
+        best_zc = c->zchunk;
       }
     }
     return BRLS_OK;
@@ -1875,11 +1998,15 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
   if (rc) {  // restore the previous choice
     c->resident_grid = saved_rg;
     c->adj_resident_grid = saved_arg;
+    c->zchunk = saved_zc;
+    set_variant_geo(c, c->variant);
     (void)set_tile_impl(c, saved_v, saved_pb, saved_apb);
     return rc;
   }
   c->resident_grid = best_rg;
   c->adj_resident_grid = best_arg;
+  c->zchunk = best_zc;
+  set_variant_geo(c, c->variant);
   if ((rc = set_tile_impl(c, best_v, best_pb, best_apb))) return rc;
   if (best) *best = best_v;
   return BRLS_OK;
@@ -1892,8 +2019,8 @@ int brls_set_tuning(brls_ctx* c, int32_t variant, int32_t born_pb,
     return fail(c, BRLS_EINVAL, "shots per block must be >= 1");
   const int rc = set_tile_impl(c, variant, born_pb, adj_pb);
   if (rc) return rc;
-  c->resident_grid = born_grid & 3;
-  c->adj_resident_grid = adj_grid & 3;
+  c->resident_grid = born_grid & 7;
+  c->adj_resident_grid = adj_grid & 7;
   return BRLS_OK;
 }
 

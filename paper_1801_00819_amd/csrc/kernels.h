@@ -11,7 +11,9 @@ struct TileShape {
   int tx, tz, ntz;  // tile width (x), tile height (z), thread rows
                     // (z-marching: rows of loads in flight ahead)
   int pipe;         // 0: staged tile; 1: staged, next shot's loads issued
-                    // before computing the current; 2: z-marching
+                    // before computing the current; 2: z-marching; 3: two
+                    // steps per launch, one chunk per work item; 4: two
+                    // steps per launch, a segment of tz rows per wavefront
 };
 
 int tile_shape_count();
@@ -43,6 +45,33 @@ hipError_t launch_march2d(int cz, int ahead, int mode, const StepArgs& a,
 // adjoint modes.
 hipError_t launch_march2t(int cz, int ahead, int mode, const StepArgs& a,
                           hipStream_t st);
+
+// Two time steps per launch, 2-D, a wavefront marching a segment of seg
+// output rows (16, 20, 24 or 32) of a 56-column strip for one shot, the
+// loads of `ahead` rows in flight; blocks of per_block wavefronts on one
+// segment.
+hipError_t launch_march2s(int seg, int ahead, int mode, const StepArgs& a,
+                          hipStream_t st);
+
+// Persistent form (Born and adjoint): one launch runs every two-step
+// launch of an operator application in turn, with a grid barrier between
+// them, on a grid no larger than what is resident at once.
+struct PersistArgs {
+  unsigned* counter;  // barrier arrivals; zero before the launch
+  int* error;         // set to 1 when a barrier wait gave up
+  int nlaunch;        // two-step launches
+  int k_hi, k_lo;     // adjoint: output levels k_hi down to k_lo
+  int nt_max;         // Born: input levels 0 .. nt_max - 2
+  int spin_limit;     // polls before a barrier wait gives up
+};
+hipError_t launch_march2s_persistent(int seg, int ahead, int mode,
+                                     const StepArgs& a, const PersistArgs& p,
+                                     hipStream_t st);
+// Blocks of the persistent kernel resident at once on the current device.
+int march2s_persistent_capacity(int seg, int ahead, int mode, int per_block);
+// Fill n unsigned ints with v (a kernel, so a graph can replay it).
+hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v,
+                           hipStream_t st);
 
 // One time step for all shots of `a` (mode: StepMode).
 hipError_t launch_step2d(int variant, int mode, const StepArgs& a,

@@ -385,10 +385,12 @@ __global__ void __launch_bounds__(kLanes* kWaves) k_march2t(StepArgs a) {
     hi = xcd * q + min(xcd, r) + q + (xcd < r ? 1 : 0);
     stride = (int)(gridDim.x >> 3) * kWaves;
   }
+  const bool xfast = (a.resident_grid & 4) != 0;  // see k_march2s
   for (int L = first; L < hi; L += stride) {
     const int grp = L % a.ngroups;
     const int tl = L / a.ngroups;
-    const int tzi = tl % g.ntz, txi = tl / g.ntz;
+    const int tzi = xfast ? tl / g.ntx : tl % g.ntz;
+    const int txi = xfast ? tl % g.ntx : tl / g.ntz;
     const int z0 = tzi * CZ;
     const int x0 = g.x_org + txi * kCore;
     const int t = tzi * g.ntx + txi;
@@ -431,10 +433,12 @@ __global__ void __launch_bounds__(kLanes* P) k_march2t_coop(StepArgs a) {
     hi = xcd * q + min(xcd, r) + q + (xcd < r ? 1 : 0);
     stride = (int)(gridDim.x >> 3);
   }
+  const bool xfast = (a.resident_grid & 4) != 0;  // see k_march2s
   for (int L = first; L < hi; L += stride) {
     const int grp = L % a.ngroups;
     const int tl = L / a.ngroups;
-    const int tzi = tl % g.ntz, txi = tl / g.ntz;
+    const int tzi = xfast ? tl / g.ntx : tl % g.ntz;
+    const int txi = xfast ? tl % g.ntx : tl / g.ntz;
     const int z0 = tzi * CZ;
     const int x0 = g.x_org + txi * kCore;
     const int t = tzi * g.ntx + txi;

@@ -409,7 +409,8 @@ static const TileShape kShapes[] = {
     {32, 16, 4, 1}, {64, 32, 8, 1}, {64, 8, 2, 1},  {64, 16, 2, 2},
     {64, 32, 2, 2}, {64, 16, 4, 2}, {64, 32, 4, 2}, {64, 8, 2, 2},
     {64, 8, 4, 2},  {56, 16, 2, 3}, {56, 16, 4, 3}, {64, 12, 2, 2},
-    {64, 12, 4, 2},
+    {64, 12, 4, 2},  {56, 20, 4, 4}, {56, 24, 4, 4}, {56, 32, 4, 4},
+    {56, 16, 4, 4},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -482,6 +483,10 @@ hipError_t launch_step2d(int variant, int mode, const StepArgs& a,
     case 18: return launch_march2t(16, 4, mode, a, st);
     case 19: return launch_march2d(12, 2, mode, a, st);
     case 20: return launch_march2d(12, 4, mode, a, st);
+    case 21: return launch_march2s(20, 4, mode, a, st);
+    case 22: return launch_march2s(24, 4, mode, a, st);
+    case 23: return launch_march2s(32, 4, mode, a, st);
+    case 24: return launch_march2s(16, 4, mode, a, st);
   }
   return hipErrorInvalidValue;
 }

@@ -70,7 +70,7 @@ def test_adjoint_matches_oracle(P, name, mode, ckpt):
     ctx.close()
 
 
-N_VARIANTS = 21
+N_VARIANTS = 25
 
 
 def test_variant_list_is_covered(P):
@@ -83,7 +83,7 @@ def test_every_tile_shape_matches_oracle(P, variant, ckpt):
     w, idx = _case("ragged2d")
     print(f"tile variant {variant} ckpt={ckpt}", flush=True)
     ctx = open_ctx(w, q_max=3, ckpt_interval=ckpt)
-    if ckpt and P.tile_variants()[variant][3] == 3:
+    if ckpt and P.tile_variants()[variant][3] >= 3:
         # two steps per launch need the stored Born sources
         with pytest.raises(P.BrlsError) as e:
             ctx.set_tuning(variant, 1, 0, 1, 0)
@@ -156,7 +156,7 @@ def _dense_receivers():
                           lam_rel=0.01)
 
 
-@pytest.mark.parametrize("variant", [0, 6, 11, 12, 13, 14, 17, 18])
+@pytest.mark.parametrize("variant", [0, 6, 11, 12, 13, 14, 17, 18, 21, 23])
 def test_dense_receivers_match_oracle(P, variant):
     w = _dense_receivers()
     idx = [0, 1]
