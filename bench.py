@@ -112,6 +112,9 @@ def parse():
     ap.add_argument("--stream-forgetting", type=float, default=0.8,
                     help="stream workload: forgetting factor of the "
                          "weighted-window run (shot weights beta^age)")
+    ap.add_argument("--no-stream-options", action="store_true",
+                    help="stream workload: skip the correction-regularised "
+                         "and weighted-window runs")
     ap.add_argument("--stream-plain-windows", type=int, default=4,
                     help="stream workload: windows run with plain launches")
     ap.add_argument("--fr-windows", type=int, default=3,
@@ -126,6 +129,12 @@ def parse():
     ap.add_argument("--cpu-sample-shots", type=int, default=2)
     ap.add_argument("--cpu-sample-nt3d", type=int, default=100,
                     help="3d workload: time steps of the oracle sample")
+    ap.add_argument("--chain3d-windows", type=int, default=0,
+                    help="3d workload: windows of the chain solved to a "
+                         "fixed residual (0: skip)")
+    ap.add_argument("--chain3d-iters", type=int, default=5,
+                    help="3d workload: CG iterations that set the fixed "
+                         "residual on window 0")
     ap.add_argument("--only-steps", action="store_true",
                     help="time the steps only (for profiler runs)")
     ap.add_argument("--workload", default="2d",
@@ -386,6 +395,8 @@ def bench_3d(args, P, synth, torch):
         roof[kind] = dict(avg_us=avg * 1e6, bytes=b, gbs=b / avg / 1e9)
     mem = ctx.memory_bytes()
     ctx.close()
+    chain = window_chain_3d(args, P, w, m, vel, torch) \
+        if args.chain3d_windows > 0 else None
     pair = 2 * Q * npad * (nt - 1)
     dom = max(roof, key=lambda k: roof[k]["avg_us"])
     out = {
@@ -424,6 +435,7 @@ def bench_3d(args, P, synth, torch):
                             "Gpt_updates_per_s":
                                 round(pair / res["plain"] / 1e9, 3)}
                            if "plain" in res else None),
+        "window_chain": chain,
     }
     if not args.no_cpu_baseline:
         # the oracle on one shot at a bounded length (one Born and one
@@ -449,6 +461,115 @@ def bench_3d(args, P, synth, torch):
         }
         log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
+
+
+def window_chain_3d(args, P, w, m, vel, torch):
+    """The 3-D block-row chain: windows of 8 shots sliding by 4, data
+    A m_true + 1 % noise synthesised on the GPU, lambda 1e-3 of a 2-step
+    power estimate of ||A_w0^T A_w0||. Window 0 runs --chain3d-iters CG
+    iterations with graph launches; the ratio ||s|| / ||A^T d|| it reaches
+    is the fixed residual tau. The next windows (warm-started, graph) and
+    window 0 again with plain per-shot launches are solved to tau; seconds
+    per window and iterations are reported."""
+    Q, S = w.Q, w.S
+    nt, nrec = w.nt, w.shots[0].nrec
+    nwin = args.chain3d_windows
+    wins = w.windows()[:nwin]
+    shots = sorted({i for win in wins for i in win})
+    t0 = time.perf_counter()
+    ctx = P.brls_open(3, w.nz, w.ny, w.nx, w.nb, nt, nrec, Q, w.h, w.dt, 0.0,
+                      vel, device=True, ckpt_interval=-1)
+    ctx.set_tile(DEFAULT_TILE3)
+    data = {}
+    for b in range(0, len(shots), Q):
+        ids = shots[b:b + Q]
+        for i in ids:
+            s = w.shots[i]
+            ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
+        d = ctx.apply_born(m)
+        off = 0
+        for i in ctx.window():
+            s = w.shots[i]
+            n = s.nt * s.nrec
+            data[i] = d[off:off + n].clone()
+            off += n
+        for i in ids:
+            ctx.downdate(i)
+    rms = float(np.sqrt(sum(float((x.double() ** 2).sum())
+                            for x in data.values())
+                        / sum(x.numel() for x in data.values())))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3001)
+    for i in shots:
+        data[i] += 0.01 * rms * torch.randn(data[i].shape, generator=gen,
+                                            device="cuda")
+    for i in wins[0]:
+        s = w.shots[i]
+        ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+    x = torch.from_numpy(synth_gaussian(w.model_shape, 2002)).cuda()
+    x /= torch.linalg.vector_norm(x)
+    nrm = 0.0
+    for _ in range(2):
+        y = ctx.apply_adjoint(ctx.apply_born(x))
+        nrm = float(torch.linalg.vector_norm(y.double()))
+        x = y / nrm
+    ctx.close()
+    torch.cuda.synchronize()
+    log(f"3d chain: data of {len(shots)} shots and lambda in "
+        f"{time.perf_counter() - t0:.1f}s")
+    lam = w.lam_rel * nrm
+
+    def solve(exec_mode, ks, rtol, iters):
+        c = P.brls_open(3, w.nz, w.ny, w.nx, w.nb, nt, nrec, Q, w.h, w.dt,
+                        lam, vel, device=True, ckpt_interval=-1)
+        c.set_tile(DEFAULT_TILE3)
+        c.set_exec(exec_mode)
+        held, out = [], []
+        for k in ks:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for i in list(held):
+                if i not in wins[k]:
+                    c.downdate(i)
+                    held.remove(i)
+            for i in wins[k]:
+                if i not in held:
+                    s = w.shots[i]
+                    c.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+                    held.append(i)
+            st = c.solve_window(iters, rtol=rtol)
+            torch.cuda.synchronize()
+            out.append(dict(window=k, seconds=round(time.perf_counter() - t,
+                                                    2),
+                            iters=st["iters"],
+                            s_over_ref=(st["s_norm"] / st["ref_norm"]
+                                        if st["ref_norm"] > 0 else None)))
+            log(f"3d chain {exec_mode} window {k}: {out[-1]}")
+        c.close()
+        return out
+
+    first = solve(P.BRLS_EXEC_GRAPH, [0], 1e-12, args.chain3d_iters)
+    tau = first[0]["s_over_ref"]
+    graph = solve(P.BRLS_EXEC_GRAPH, list(range(nwin)), tau, 1000)
+    plain = solve(P.BRLS_EXEC_PLAIN, [0], tau, 1000) \
+        if not args.no_plain else None
+    return {
+        "windows": [list(x) for x in wins],
+        "lambda": lam,
+        "tau": tau,
+        "tau_from": f"window 0 after {args.chain3d_iters} iterations",
+        "graph": graph,
+        "graph_s_per_window_mean": round(
+            float(np.mean([x["seconds"] for x in graph])), 2),
+        "plain_window0": plain,
+        "note": "each window's seconds include the new shots' background "
+                "checkpoints; plain = one launch per shot and time step",
+    }
+
+
+def synth_gaussian(shape, seed):
+    import synth
+    return synth.gaussian(shape, seed).astype(np.float32)
 
 
 def bench_autograd(args, P, synth, torch):
@@ -636,6 +757,9 @@ def bench_stream(args, P, synth, torch):
             chg.append(float(torch.linalg.vector_norm(img - prev)
                              / torch.linalg.vector_norm(img)))
             prev.copy_(image)
+            if k % 16 == 15:
+                log(f"stream Q={Q} exec {exec_mode}: window {k + 1}/"
+                    f"{len(wins)}, latency {lat[-1]:.3f}s")
         c.close()
         return lat, len(w.windows()), err, chg
 
@@ -666,17 +790,21 @@ def bench_stream(args, P, synth, torch):
         per_q[Q]["plain_p50_s"] = round(
             float(np.percentile(plain[1:] or plain, 50)), 4)
         log(f"stream Q={Q}: {per_q[Q]}")
-    # the correction-regularised recursion (damping towards the previous
-    # window's image instead of towards zero) on the same Q = 8 stream
-    lat, _, err, chg = run(8, P.BRLS_EXEC_GRAPH, 10 ** 9, regularize=1)
-    corr = summary(lat, err, chg)
-    log(f"stream Q=8 correction-regularised: {corr}")
-    # and with each shot's misfit weighted by beta^age (forgetting factor)
-    lat, _, err, chg = run(8, P.BRLS_EXEC_GRAPH, 10 ** 9, regularize=1,
-                           forgetting=args.stream_forgetting)
-    forget = summary(lat, err, chg)
-    forget["beta"] = args.stream_forgetting
-    log(f"stream Q=8 correction-regularised, weighted window: {forget}")
+    corr = forget = None
+    if not args.no_stream_options:
+        # the correction-regularised recursion (damping towards the
+        # previous window's image instead of towards zero) on the same
+        # Q = 8 stream
+        lat, _, err, chg = run(8, P.BRLS_EXEC_GRAPH, 10 ** 9, regularize=1)
+        corr = summary(lat, err, chg)
+        log(f"stream Q=8 correction-regularised: {corr}")
+        # and with each shot's misfit weighted by beta^age (forgetting
+        # factor)
+        lat, _, err, chg = run(8, P.BRLS_EXEC_GRAPH, 10 ** 9, regularize=1,
+                               forgetting=args.stream_forgetting)
+        forget = summary(lat, err, chg)
+        forget["beta"] = args.stream_forgetting
+        log(f"stream Q=8 correction-regularised, weighted window: {forget}")
     out = {
         "metric": "window solve latency p50 (Q=8)",
         "value": per_q[8]["p50_s"],

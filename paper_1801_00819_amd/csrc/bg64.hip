@@ -12,11 +12,12 @@
 // u^{n+1} = u^n + v^{n+1}, frame n = W'(h^2 L u^n + h^2 f(t_n) e_s) (where
 // C1 = C2 = 1, i.e. on the model region).
 //
-// One thread per padded point; the 4-cell zero ring around the padded grid
-// (same storage layout as the float32 fields, float64 elements) supplies the
-// Dirichlet boundary, so no load is bounds-checked. Neighbour reuse is left
-// to the L1/L2 caches: this kernel runs nt - 1 times per new shot, not per
-// CG iteration.
+// The 4-cell zero ring around the padded grid (same storage layout as the
+// float32 fields, float64 elements) supplies the Dirichlet boundary, so no
+// load is bounds-checked. 3-D: one thread per padded point, neighbour reuse
+// left to the caches; 2-D: a thread marches a column (k_background64_2d).
+// These kernels run nt - 1 times per shot entering the window, not per CG
+// iteration.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -76,10 +77,68 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// 2-D form: each thread marches one column down a chunk of kBgRows rows,
+// keeping the column's nine u values the z-stencil needs in registers (one
+// new row loaded per point), the x-neighbours read from the same row (the
+// block's neighbouring columns: cache hits). Same arithmetic, in the same
+// order, as k_background64.
+constexpr int kBgRows = 32;
+
+__global__ void __launch_bounds__(256)
+    k_background64_2d(Bg64Args a, const Bg64Shot* tab, int n) {
+  const Bg64Shot sd = tab[blockIdx.z];
+  if (n >= sd.nt - 1) return;
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= a.px) return;
+  const int z0 = blockIdx.y * kBgRows;
+  const int z1 = min(z0 + kBgRows, a.pz);
+  const int64_t sz = a.pitch;
+  const double* u = sd.u[n & 1];
+  double* uo = sd.u[(n + 1) & 1];
+  const int dx = depth(x, a.nb, a.nx);
+  const bool inx = dx == 0;
+  // q[k]: u at row z - 4 + k, k = 0..8
+  double q[9];
+  int64_t i = (int64_t)(z0 + kGhost - 4) * sz + x + a.xoff;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) q[k] = u[i + k * sz];
+  i += 4 * sz;  // row z0
+  for (int z = z0; z < z1; ++z, i += sz) {
+    q[8] = u[i + 4 * sz];
+    const double c = q[4];
+    double lap = 0.0;
+#pragma unroll
+    for (int k = 4; k >= 1; --k) {
+      double t = (q[4 + k] - c) + (q[4 - k] - c);
+      t += (u[i + k] - c) + (u[i - k] - c);
+      lap = fma(a.w[k - 1], t, lap);
+    }
+    const bool src = z == sd.src_z && x == sd.src_x;
+    const double inc = a.wp[i] * (lap + (src ? sd.wav[n] : 0.0));
+    const int dz = depth(z, a.nb, a.nz);
+    const double damp = a.eta_scale * (double)(dz * dz + dx * dx);
+    const double C1 = 1.0 / (1.0 + damp), C2 = (1.0 - damp) * C1;
+    const double vn = C2 * sd.v[i] + C1 * inc;
+    sd.v[i] = vn;
+    uo[i] = c + vn;
+    if (dz == 0 && inx)
+      sd.d2[(int64_t)n * a.mplane + (int64_t)(z - a.nb) * a.nx + (x - a.nb)] =
+          (float)inc;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = q[k + 1];
+  }
+}
+
 hipError_t launch_background64(const Bg64Args& a, const Bg64Shot* tab,
                                int nshots, int n, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
-  const int rows = a.pz * (a.ndim == 3 ? a.py : 1);
+  if (a.ndim == 2) {
+    const dim3 grid((a.px + 255) / 256, (a.pz + kBgRows - 1) / kBgRows,
+                    nshots);
+    hipLaunchKernelGGL(k_background64_2d, grid, dim3(256), 0, st, a, tab, n);
+    return hipGetLastError();
+  }
+  const int rows = a.pz * a.py;
   const dim3 grid((a.px + 63) / 64, (rows + 3) / 4, nshots);
   hipLaunchKernelGGL(k_background64, grid, dim3(64, 4), 0, st, a, tab, n);
   return hipGetLastError();

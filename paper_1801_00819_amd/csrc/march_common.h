@@ -56,18 +56,26 @@ __device__ __forceinline__ Nb xnb(float c, float h) {
   return n;
 }
 
+// A shift whose vacated lane reads zero (bound_ctrl): no old value to copy
+// into the destination first.
+template <int CTRL>
+__device__ __forceinline__ float dpp0(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
 // x-neighbours for the second step of a two-step kernel, whose results at
 // the four lanes on each edge are discarded: plain shifts, no fill values.
 __device__ __forceinline__ Nb xnb_inner(float c) {
   Nb n;
-  n.m[0] = dpp<kWaveShr1>(c, c);
-  n.m[1] = dpp<kWaveShr1>(n.m[0], c);
-  n.m[2] = dpp<kWaveShr1>(n.m[1], c);
-  n.m[3] = dpp<kWaveShr1>(n.m[2], c);
-  n.p[0] = dpp<kWaveShl1>(c, c);
-  n.p[1] = dpp<kWaveShl1>(n.p[0], c);
-  n.p[2] = dpp<kWaveShl1>(n.p[1], c);
-  n.p[3] = dpp<kWaveShl1>(n.p[2], c);
+  n.m[0] = dpp0<kWaveShr1>(c);
+  n.m[1] = dpp0<kWaveShr1>(n.m[0]);
+  n.m[2] = dpp0<kWaveShr1>(n.m[1]);
+  n.m[3] = dpp0<kWaveShr1>(n.m[2]);
+  n.p[0] = dpp0<kWaveShl1>(c);
+  n.p[1] = dpp0<kWaveShl1>(n.p[0]);
+  n.p[2] = dpp0<kWaveShl1>(n.p[1]);
+  n.p[3] = dpp0<kWaveShl1>(n.p[2]);
   return n;
 }
 
