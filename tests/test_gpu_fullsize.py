@@ -10,8 +10,17 @@ The oracle's images of the chain are stored in
 ``tests/golden/make_faulted2d_chain.py`` (hours of oracle work); the data
 both sides use are regenerated here by the same oracle calls and checked
 against the hash stored with the images.
+
+Truncated damped CG is sensitive to rounding at this size: the oracle's own
+20th iterate moves by percents when only its operator operands and results
+are rounded to float32 (the stored ``images_r32``), from about the 8th
+iteration on. So the chain is checked twice: the 7th iterate of the first
+window, before that sensitivity sets in, to 1e-4; and the 20-iteration
+images and data misfits within twice the distance between the oracle's FP64
+and float32-interface runs (never tighter than 1e-4).
 """
 import importlib.util
+import json
 import os
 
 import numpy as np
@@ -100,38 +109,83 @@ def test_full_size_adjoint_of_window_matches_oracle(inputs):
     assert e <= OP_TOL
 
 
+def _golden(digest):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("oracle images not generated "
+                    "(tests/golden/make_faulted2d_chain.py)")
+    g = np.load(GOLDEN, allow_pickle=False)
+    assert str(g["data_sha256"]) == digest, \
+        "regenerated data differ from the ones the oracle images used"
+    return g
+
+
+def _load_window(ctx, w, data, win, held):
+    for i in list(held):
+        if i not in win:
+            ctx.downdate(i)
+            held.remove(i)
+    for i in win:
+        if i not in held:
+            s = w.shots[i]
+            ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+            held.append(i)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_early_iterate_matches_oracle(inputs):
+    """The first window from a zero image, 7 CG iterations: image and
+    ||A^T r - lambda m|| against the oracle's 7th iterate, 1e-4."""
+    mk, w, prob, clean, data, digest = inputs
+    g = _golden(digest)
+    if "early" not in g.files:
+        pytest.skip("oracle's early iterate not stored")
+    k = int(g["early_k"])
+    want_s = json.loads(str(g["early_stats"]))["s_norms"][k]
+    ctx = _window_ctx(w, float(g["lam"]))
+    _load_window(ctx, w, data, mk.WINDOWS[0], [])
+    st = ctx.solve_window(k)
+    assert st["iters"] == k
+    e = rel(ctx.image(), g["early"])
+    es = abs(st["s_norm"] - want_s) / want_s
+    ctx.close()
+    print(f"iterate {k}: image vs oracle {e:.2e}, ||s|| {st['s_norm']:.6e} "
+          f"vs {want_s:.6e} ({es:.1e})")
+    assert e <= IMG_TOL and es <= IMG_TOL
+
+
 @pytest.mark.timeout(900)
 def test_full_size_chain_matches_oracle(inputs):
     """The chain's first windows (8 shots sliding by 4, 20 iterations each,
     the second warm-started from the first's image) against the oracle's
-    stored images: relative L2 <= 1e-4 per window."""
-    if not os.path.exists(GOLDEN):
-        pytest.skip("oracle images not generated "
-                    "(tests/golden/make_faulted2d_chain.py)")
+    stored images and data misfits ||d_w - A_w m||, each within
+    max(1e-4, 2 x the oracle's own FP64 vs float32-interface distance for
+    that window; the first window's where a later one is not stored)."""
     mk, w, prob, clean, data, digest = inputs
-    g = np.load(GOLDEN, allow_pickle=False)
-    assert str(g["data_sha256"]) == digest, \
-        "regenerated data differ from the ones the oracle images used"
+    g = _golden(digest)
+    if "images_r32" not in g.files:
+        pytest.skip("oracle's float32-interface chain not stored")
     lam = float(g["lam"])
-    images = g["images"]
+    images, im32 = g["images"], g["images_r32"]
+    st64 = json.loads(str(g["stats"]))
+    st32 = json.loads(str(g["stats_r32"]))
     ctx = _window_ctx(w, lam)
     held = []
-    errs = []
+    fails = []
     for k in range(images.shape[0]):
-        win = mk.WINDOWS[k]
-        for i in list(held):
-            if i not in win:
-                ctx.downdate(i)
-                held.remove(i)
-        for i in win:
-            if i not in held:
-                s = w.shots[i]
-                ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
-                held.append(i)
+        j = min(k, im32.shape[0] - 1)
+        img_bound = max(IMG_TOL, 2.0 * rel(im32[j], images[j]))
+        r64, r32 = st64[j]["r_norms"][-1], st32[j]["r_norms"][-1]
+        mis_bound = max(IMG_TOL, 2.0 * abs(r32 - r64) / r64)
+        _load_window(ctx, w, data, mk.WINDOWS[k], held)
         st = ctx.solve_window(mk.NITER)
         assert st["iters"] == mk.NITER
-        errs.append(rel(ctx.image(), images[k]))
-        print(f"window {k}: image vs oracle {errs[-1]:.2e}, ||s|| "
-              f"{st['s0_norm']:.4e} -> {st['s_norm']:.4e}", flush=True)
+        e = rel(ctx.image(), images[k])
+        want_r = st64[k]["r_norms"][-1]
+        er = abs(st["r_norm"] - want_r) / want_r
+        print(f"window {k}: image vs oracle {e:.2e} (bound {img_bound:.2e}), "
+              f"misfit {st['r_norm']:.6e} vs {want_r:.6e}: {er:.2e} "
+              f"(bound {mis_bound:.2e})", flush=True)
+        if e > img_bound or er > mis_bound:
+            fails.append(k)
     ctx.close()
-    assert max(errs) <= IMG_TOL
+    assert not fails, f"windows {fails} outside the oracle's own spread"
