@@ -189,3 +189,38 @@ def test_full_size_chain_matches_oracle(inputs):
             fails.append(k)
     ctx.close()
     assert not fails, f"windows {fails} outside the oracle's own spread"
+
+
+STREAM_GOLDEN = os.path.join(HERE, "golden", "stream2d_512x1024_q4_chain2.npz")
+
+
+@pytest.mark.timeout(900)
+def test_full_size_stream_chain_matches_oracle():
+    """The 512-shot streaming form at full size, windows of 4 sliding by 2
+    (shots 0-3, then 2-5: ragged nt 2000 / 3000 and 304 .. 1022 receivers,
+    each shot's data from its own drifted model), 5 iterations per window
+    warm-started, in the bench's launch choice: both images against the
+    oracle's stored ones (``tests/golden/make_stream2d_chain.py``), 1e-4."""
+    spec = importlib.util.spec_from_file_location(
+        "make_stream2d_chain",
+        os.path.join(HERE, "golden", "make_stream2d_chain.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    w, prob = mk.problem()
+    print("oracle: data of the stream's shots 0-5 at full size", flush=True)
+    data, digest = mk.stream_inputs(w, prob)
+    g = np.load(STREAM_GOLDEN, allow_pickle=False)
+    assert str(g["data_sha256"]) == digest, \
+        "regenerated data differ from the ones the oracle images used"
+    ctx = open_ctx(w, lam=float(g["lam"]), q_max=mk.Q)
+    ctx.set_tuning(*_bench_tuning())
+    held, errs = [], []
+    for k, win in enumerate(mk.WINDOWS):
+        _load_window(ctx, w, data, win, held)
+        st = ctx.solve_window(mk.NITER)
+        assert st["iters"] == mk.NITER
+        errs.append(rel(ctx.image(), g["images"][k]))
+        print(f"stream window {k} (shots {win}): image vs oracle "
+              f"{errs[-1]:.2e}", flush=True)
+    ctx.close()
+    assert max(errs) <= IMG_TOL
