@@ -120,6 +120,8 @@ def parse():
                     help="stream workload: windows run with plain launches")
     ap.add_argument("--fr-windows", type=int, default=3,
                     help="windows solved to a fixed residual (0: skip)")
+    ap.add_argument("--no-small-chain", action="store_true",
+                    help="skip the 64 x 64 chain in every execution mode")
     ap.add_argument("--no-host-window", action="store_true",
                     help="skip the window solved through host pointers "
                          "(PCIe-inclusive rate)")
@@ -197,6 +199,119 @@ def point_step_bytes(kind, B):
     16 + 4 / B (the image accumulator held on chip; the Born-source frame
     counted in neither, as in the per-step count of the design)."""
     return 16.0 + (8.0 if kind == "born" else 4.0) / B
+
+
+def small_chain(P, synth, torch, reps=5):
+    """The launch-bound 64 x 64 chain (4 shots, windows of 2 sliding by 1,
+    10 CG iterations each, lambda 0.01 relative to a power estimate of the
+    first window): seconds for the whole chain from a zero image (updates,
+    downdates, backgrounds, solves, image out) in each execution mode, the
+    data synthesised by the library's Born + 1 % noise. Also the largest
+    relative distance between the modes' final images."""
+    w = synth.layers2d_64x64()
+    vel = w.vel.astype(np.float32)
+    nrec = w.shots[0].nrec
+    m_true = torch.from_numpy(w.m_true.astype(np.float32)).cuda()
+    n = len(w.shots)
+    ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, w.nt, nrec, n, w.h, w.dt, 0.0,
+                      vel, device=True)
+    ctx.set_tuning(*DEFAULT_TUNING)
+    for s in w.shots:
+        ctx.update(s.id, s.src, s.rec, s.nt, s.f0, None)
+    data = ctx.apply_born(m_true).view(n, w.nt, nrec).clone()
+    ctx.close()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    rms = float(torch.sqrt(torch.mean(data.double() ** 2)))
+    data += w.noise_rel * rms * torch.randn(data.shape, generator=gen,
+                                            device="cuda")
+    windows = w.windows()
+    ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, w.nt, nrec, w.Q, w.h, w.dt,
+                      0.0, vel, device=True)
+    ctx.set_tuning(*DEFAULT_TUNING)
+    for i in windows[0]:
+        s = w.shots[i]
+        ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+    x = torch.from_numpy(synth.gaussian(w.model_shape, 2002).astype(
+        np.float32)).cuda()
+    x /= torch.linalg.vector_norm(x)
+    norm = 0.0
+    for _ in range(8):
+        y = ctx.apply_adjoint(ctx.apply_born(x))
+        norm = float(torch.linalg.vector_norm(y.double()))
+        x = y / norm
+    ctx.close()
+    lam = w.lam_rel * norm
+    zero = torch.zeros(w.model_shape, dtype=torch.float32, device="cuda")
+    image = torch.empty_like(zero)
+    out, images = {}, {}
+    for mode, name in ((P.BRLS_EXEC_PLAIN, "plain"),
+                       (P.BRLS_EXEC_BATCHED, "batched"),
+                       (P.BRLS_EXEC_GRAPH, "graph"),
+                       (P.BRLS_EXEC_PERSISTENT, "persistent")):
+        ctx = P.brls_open(2, w.nz, 1, w.nx, w.nb, w.nt, nrec, w.Q, w.h,
+                          w.dt, lam, vel, device=True)
+        ctx.set_tuning(*DEFAULT_TUNING)
+        ctx.set_exec(mode)
+
+        def chain():
+            held = []
+            ctx.set_image(zero)
+            for win in windows:
+                for i in list(held):
+                    if i not in win:
+                        ctx.downdate(i)
+                        held.remove(i)
+                for i in win:
+                    if i not in held:
+                        s = w.shots[i]
+                        ctx.update(i, s.src, s.rec, s.nt, s.f0, data[i])
+                        held.append(i)
+                ctx.solve_window(w.niter)
+            ctx.image(image)
+            for i in held:
+                ctx.downdate(i)
+
+        chain()  # graph capture and first-touch outside the timing
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            chain()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / reps
+        images[name] = image.clone()
+        ctx.close()
+        out[name] = {"s_per_chain": round(sec, 5),
+                     "ms_per_window": round(sec / len(windows) * 1e3, 3)}
+        log(f"64x64 chain, {name}: {out[name]}")
+    ref = images["graph"]
+    out["max_rel_diff_between_modes"] = float(max(
+        torch.linalg.vector_norm((v - ref).double()) /
+        torch.linalg.vector_norm(ref.double()) for v in images.values()))
+    out["windows"] = len(windows)
+    out["cg_iters"] = w.niter
+    out["lam"] = lam
+    return out
+
+
+def oracle_small_chain(synth):
+    """The FP64 oracle on the same 64 x 64 chain, on its own inputs (oracle
+    Born of the model + 1 % seeded noise, lambda from an 8-step power
+    estimate): seconds for the whole chain, and for those inputs."""
+    import oracle
+    w = synth.layers2d_64x64()
+    prob = oracle.Problem.from_workload(w)
+    t = time.perf_counter()
+    r = np.random.default_rng(7)
+    noise = [r.standard_normal(prob.data_shape(i))
+             for i in range(len(w.shots))]
+    data = oracle.synthesize_data(prob, w.m_true, w.noise_rel, noise)
+    lam = w.lam_rel * oracle.power_norm(prob, w.windows()[0], 8, seed=2002)
+    t_in = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.chain(prob, data, w.windows(), lam, w.niter)
+    return {"s_per_chain": round(time.perf_counter() - t, 3),
+            "inputs_s": round(t_in, 3)}
 
 
 def fixed_residual(args, P, w, data, lam, vel, torch):
@@ -1403,6 +1518,11 @@ def main():
                                            torch)
         log(f"host pointers: {out['host_pointers']}")
 
+    # ---- the launch-bound 64 x 64 chain in every execution mode ---------
+    if not args.no_small_chain:
+        out["small_chain"] = small_chain(P, synth, torch)
+        log(f"64x64 chain: {out['small_chain']}")
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample -------------
     if not args.no_cpu_baseline:
         import oracle
@@ -1426,6 +1546,8 @@ def main():
             "sample": f"{nsh} shots, nt={ns} (of {nt}), one Born + one "
                       f"adjoint application each, FP64, {tc:.1f}s",
         }
+        if "small_chain" in out:
+            out["cpu_baseline"]["small_chain"] = oracle_small_chain(synth)
         log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
