@@ -78,7 +78,8 @@ def test_full_size_gradient_vs_finite_differences(big_window):
     of ||m||. Directions are Gaussian fields smoothed over 4 cells: white
     noise lies mostly outside the band the Born operator sees, where the
     float32 rounding of the two misfit evaluations dominates their small
-    difference. Compared as a vector over the 16 directions."""
+    difference. Compared as a vector over the 16 directions, and each
+    direction against the largest directional derivative."""
     import torch
     from scipy.ndimage import gaussian_filter
 
@@ -107,9 +108,15 @@ def test_full_size_gradient_vs_finite_differences(big_window):
         ans.append(float(torch.sum(g * p_eff)))
     fds, ans = np.array(fds), np.array(ans)
     err = np.linalg.norm(fds - ans) / np.linalg.norm(ans)
-    print(f"FD vs autograd over 16 directions: rel L2 {err:.2e}, "
-          f"worst single {np.max(np.abs(fds - ans) / np.abs(ans)):.2e}")
+    worst = np.max(np.abs(fds - ans)) / np.max(np.abs(ans))
+    print(f"FD vs autograd over 16 directions: rel L2 {err:.2e}, worst "
+          f"direction {worst:.2e} of the largest directional derivative, "
+          f"worst own-relative {np.max(np.abs(fds - ans) / np.abs(ans)):.2e}")
     assert err <= 1e-4
+    # every direction, against the common scale of the directional
+    # derivatives (a direction nearly orthogonal to the gradient has a tiny
+    # derivative that the misfits' rounding dominates)
+    assert worst <= 1e-4
 
 
 def test_full_size_gradient_matches_oracle_adjoint_one_shot(big_window):
