@@ -177,6 +177,14 @@ int brls_window_data_size(const brls_ctx* ctx, int64_t* n);
 int brls_solve_window(brls_ctx* ctx, int32_t max_iter, double rtol,
                       brls_stats* stats);
 
+/* The CG recurrences of the last brls_solve_window (eq. 10's solve): per
+ * iteration k = 1 .. n, alpha_k, beta_k and ||A^T r_k - lambda m_k||
+ * (the damping term as in brls_solve_window). *n receives the iteration
+ * count; each non-NULL array (host memory) receives min(n, cap) values.
+ * Errors: BRLS_EINVAL (n NULL, cap < 0). */
+int brls_solve_history(brls_ctx* ctx, int32_t cap, double* alpha,
+                       double* beta, double* s_norm, int32_t* n);
+
 /* Copy the current image [nz][ny][nx] out (synchronises the stream): the
  * window's solution of eq. 10, m after the last window being the chain's
  * result (Fig. 2d). */

@@ -152,6 +152,22 @@ class Context:
 
     solve_window = brls_solve_window
 
+    def brls_solve_history(self) -> dict:
+        """alpha, beta and ||s|| per iteration of the last solve."""
+        n = ctypes.c_int32()
+        self._check(L.lib().brls_solve_history(self._h, 0, None, None, None,
+                                               ctypes.byref(n)))
+        k = n.value
+        out = {x: np.zeros(k, np.float64) for x in ("alpha", "beta",
+                                                     "s_norm")}
+        if k:
+            self._check(L.lib().brls_solve_history(
+                self._h, k, out["alpha"].ctypes.data, out["beta"].ctypes.data,
+                out["s_norm"].ctypes.data, ctypes.byref(n)))
+        return out
+
+    solve_history = brls_solve_history
+
     def _model_out(self, out):
         if out is not None:
             return out

@@ -100,6 +100,8 @@ SIGNATURES = [
     ("brls_window_data_size", _I32, [_VP, ctypes.POINTER(_I64)]),
     ("brls_solve_window", _I32, [_VP, _I32, ctypes.c_double,
                                  ctypes.POINTER(brls_stats)]),
+    ("brls_solve_history", _I32, [_VP, _I32, _VP, _VP, _VP,
+                                  ctypes.POINTER(_I32)]),
     ("brls_image", _I32, [_VP, _VP]),
     ("brls_set_image", _I32, [_VP, _VP]),
     ("brls_image64", _I32, [_VP, _VP]),

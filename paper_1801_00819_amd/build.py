@@ -16,6 +16,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+# roctx ranges (window solves, CG iterations, updates, operators)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def _compile(hipcc, src, obj, verbose):
@@ -40,7 +42,7 @@ def build(verbose: bool = False) -> str:
                   for s, o in zip(srcs, objs)]:
             f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + ["-shared", "-o", tmp] + objs
+    cmd = [hipcc] + FLAGS + ["-shared", "-o", tmp] + objs + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -21,6 +21,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "brrlsm.h"
 #include "kernels.h"
 #include "layout.h"
@@ -28,6 +30,16 @@
 using namespace brls;
 
 namespace {
+
+// A roctx range over a scope (window solves, CG iterations, window
+// updates, background builds, operator applications): visible in a
+// rocprofv3 trace with --marker-trace, a no-op otherwise.
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // 8th-order central second-derivative weights (offsets 1..4); the
 // difference-form stencil needs no centre weight.
@@ -164,6 +176,7 @@ struct brls_ctx {
   float *dobs = nullptr, *r = nullptr, *q = nullptr, *dscr = nullptr;
   float* wslot = nullptr;  // [q_max] per-slot misfit weights (device)
   std::vector<float> wslot_h;  // their host copy, uploaded by the solve
+  std::vector<double> hist;    // last solve: (alpha, beta, ||s||) per iter
   double *partial = nullptr, *scal = nullptr;
   int* flag = nullptr;
   ShotDev* tab_dev = nullptr;
@@ -502,6 +515,7 @@ int ensure_backgrounds(brls_ctx* c) {
   for (int i : c->order)
     if (!c->slots[i].bg_ready) todo.push_back(i);
   if (todo.empty()) return BRLS_OK;
+  Range range("brls background build");
   std::vector<ShotDev> tab;
   for (int i : todo) tab.push_back(shot_dev(c, c->slots[i]));
   HIPCHECK(c, hipStreamSynchronize(c->st));
@@ -1155,6 +1169,7 @@ const char* brls_last_error(const brls_ctx* c) {
 
 int brls_update(brls_ctx* c, const brls_shot* sh) {
   if (!c || !sh) return fail(c, BRLS_EINVAL, "NULL argument");
+  Range range("brls_update");
   if (find_slot(c, sh->id) >= 0)
     return fail(c, BRLS_EDUP, "shot %lld already in the window",
                 (long long)sh->id);
@@ -1244,6 +1259,7 @@ int brls_update(brls_ctx* c, const brls_shot* sh) {
 
 int brls_downdate(brls_ctx* c, int64_t id) {
   if (!c) return BRLS_EINVAL;
+  Range range("brls_downdate");
   const int i = find_slot(c, id);
   if (i < 0)
     return fail(c, BRLS_ENOSHOT, "no shot %lld in the window", (long long)id);
@@ -1359,6 +1375,7 @@ int solve_window64(brls_ctx* c, int32_t max_iter, double rtol,
   for (int it = 0; it < max_iter; ++it) {
     if (gamma == 0.0) break;
     if (rtol > 0 && snorm <= rtol * ref) break;
+    Range range("brls CG iteration");
     if ((rc = born64(c->p64))) return rc;
     if (weighted)
       HIPCHECK(c, launch_scale_segments(c->dscr, c->q, c->wslot, c->seg, D,
@@ -1395,6 +1412,7 @@ int solve_window64(brls_ctx* c, int32_t max_iter, double rtol,
     snorm = std::sqrt(sc[0]);
     st->iters = it + 1;
     st->s_norm = snorm;
+    c->hist.insert(c->hist.end(), {alpha, beta, snorm});
   }
   HIPCHECK(c, launch_dot_d(c->r64, c->r64, D, c->partial, c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return rc;
@@ -1409,6 +1427,8 @@ int solve_window64(brls_ctx* c, int32_t max_iter, double rtol,
 int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
                       brls_stats* stats) {
   if (!c) return BRLS_EINVAL;
+  Range range("brls_solve_window");
+  c->hist.clear();
   const auto t_start = std::chrono::steady_clock::now();
   brls_stats st{};
   auto finish = [&](int code) {
@@ -1484,6 +1504,7 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
   for (int it = 0; it < max_iter; ++it) {
     if (gamma == 0.0) break;
     if (rtol > 0 && snorm <= rtol * ref) break;
+    Range range("brls CG iteration");
     if ((rc = born_of(c, c->p))) return finish(rc);
     if (weighted)
       HIPCHECK(c, launch_scale_segments(c->dscr, c->q, c->wslot, c->seg, D,
@@ -1519,12 +1540,26 @@ int brls_solve_window(brls_ctx* c, int32_t max_iter, double rtol,
     snorm = std::sqrt(sc[0]);
     st.iters = it + 1;
     st.s_norm = snorm;
+    c->hist.insert(c->hist.end(), {alpha, beta, snorm});
   }
   HIPCHECK(c, launch_dot(c->r, c->r, D, c->partial, c->scal, c->st));
   if ((rc = read_scalars(c, sc, 1))) return finish(rc);
   st.r_norm = std::sqrt(sc[0]);
   HIPCHECK(c, launch_cvt_f2d(c->m64, c->m, M, c->st));
   return finish(BRLS_OK);
+}
+
+int brls_solve_history(brls_ctx* c, int32_t cap, double* alpha,
+                       double* beta, double* s_norm, int32_t* n) {
+  if (!c || !n || cap < 0) return fail(c, BRLS_EINVAL, "bad argument");
+  const int32_t k = (int32_t)(c->hist.size() / 3);
+  *n = k;
+  for (int32_t i = 0; i < k && i < cap; ++i) {
+    if (alpha) alpha[i] = c->hist[3 * i];
+    if (beta) beta[i] = c->hist[3 * i + 1];
+    if (s_norm) s_norm[i] = c->hist[3 * i + 2];
+  }
+  return BRLS_OK;
 }
 
 int brls_set_shot_weight(brls_ctx* c, int64_t id, double w) {
@@ -1650,6 +1685,7 @@ int brls_set_image64(brls_ctx* c, const double* m) {
 
 int brls_apply_born(brls_ctx* c, const float* m, float* d_out) {
   if (!c || !m || !d_out) return fail(c, BRLS_EINVAL, "NULL argument");
+  Range range("brls_apply_born");
   HIPCHECK(c, hipMemcpyAsync(c->born_in, m, c->mplane * 4, in_kind(c), c->st));
   int rc = born_of(c, c->born_in);
   if (rc) return rc;
@@ -1705,6 +1741,7 @@ int brls_background_window(brls_ctx* c, float* out) {
 
 int brls_apply_adjoint(brls_ctx* c, const float* d, float* m_out) {
   if (!c || !d || !m_out) return fail(c, BRLS_EINVAL, "NULL argument");
+  Range range("brls_apply_adjoint");
   HIPCHECK(c, launch_fill_f32(c->dscr, (int64_t)c->g.q_max * c->seg, 0.f,
                               c->st));
   int64_t off = 0;

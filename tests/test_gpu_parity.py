@@ -4,6 +4,8 @@ Bars: relative L2 <= 1e-5 per application of A or A^T; <= 1e-4 on final
 images of a window chain. Inputs are seeded and rounded to float32 before
 either side sees them.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -317,10 +319,24 @@ def test_window_solve_matches_oracle_iterate_norms(P):
     for i in idx:
         add_shot(ctx, w, i, data[i])
     st = ctx.solve_window(5)
+    h = ctx.solve_history()
     assert abs(st["s0_norm"] - res.s0_norm) <= 1e-5 * res.s0_norm
     assert abs(st["s_norm"] - res.s_norms[-1]) <= 1e-3 * res.s_norms[-1]
     assert abs(st["r_norm"] - res.r_norms[-1]) <= 1e-5 * res.r_norms[-1]
     assert rel(ctx.image(), res.m) <= IMG_TOL
+    # the recurrences iteration by iteration (brls_solve_history)
+    assert len(h["alpha"]) == st["iters"] == 5
+    ea = np.abs(h["alpha"] / np.array(res.alphas) - 1)
+    eb = np.abs(h["beta"] / np.array(res.betas) - 1)
+    es = np.abs(h["s_norm"] / np.array(res.s_norms[1:]) - 1)
+    print(f"per iteration: alpha {ea.max():.1e}, beta {eb.max():.1e}, "
+          f"||s|| {es.max():.1e}")
+    assert h["s_norm"][-1] == st["s_norm"]
+    assert ea.max() <= 1e-4 and eb.max() <= 1e-4 and es.max() <= 1e-4
+    from paper_1801_00819_amd import _lib as L
+    n = ctypes.c_int32()
+    assert L.lib().brls_solve_history(ctx._h, -1, None, None, None,
+                                      ctypes.byref(n)) == L.BRLS_EINVAL
     ctx.close()
 
 

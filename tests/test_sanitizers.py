@@ -62,7 +62,7 @@ def test_abi_checks_under_asan_ubsan(tmp_path):
                                              os.path.join(HERE,
                                                           "abi_checks.cpp")])
     exe = str(tmp_path / "abi_checks")
-    _run([HIPCC] + flags + ["-o", exe, drv, eng] + others)
+    _run([HIPCC] + flags + ["-o", exe, drv, eng] + others + hipbuild.LIBS)
     # the HIP runtime's own allocations outlive main: leaks are not checked
     env = dict(SAN_ENV, ASAN_OPTIONS="detect_leaks=0")
     p = _run([exe], env=env)
