@@ -347,6 +347,19 @@ class Context:
 
     set_exec = brls_set_exec
 
+    def brls_set_chains(self, n: int):
+        """Concurrent launch chains of the batched and graph modes (1, 2)."""
+        self._check(L.lib().brls_set_chains(self._h, int(n)))
+
+    set_chains = brls_set_chains
+
+    def brls_get_chains(self) -> int:
+        n = ctypes.c_int32()
+        self._check(L.lib().brls_get_chains(self._h, ctypes.byref(n)))
+        return n.value
+
+    get_chains = brls_get_chains
+
     def brls_set_spin_limit(self, polls: int):
         """Polls before a persistent launch's barrier wait gives up."""
         self._check(L.lib().brls_set_spin_limit(self._h, int(polls)))

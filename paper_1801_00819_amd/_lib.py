@@ -102,6 +102,8 @@ SIGNATURES = [
                                  ctypes.POINTER(brls_stats)]),
     ("brls_solve_history", _I32, [_VP, _I32, _VP, _VP, _VP,
                                   ctypes.POINTER(_I32)]),
+    ("brls_set_chains", _I32, [_VP, _I32]),
+    ("brls_get_chains", _I32, [_VP, ctypes.POINTER(_I32)]),
     ("brls_image", _I32, [_VP, _VP]),
     ("brls_set_image", _I32, [_VP, _VP]),
     ("brls_image64", _I32, [_VP, _VP]),

@@ -121,8 +121,8 @@ const char* kTimerNames[kTNumKinds] = {"background_step", "born_step",
                                        "adjoint_graph"};
 
 // op, shots, shots per block, tile variant, time steps, resident grid,
-// execution mode
-using GraphKey = std::tuple<int, int, int, int, int, int, int>;
+// execution mode, chains
+using GraphKey = std::tuple<int, int, int, int, int, int, int, int>;
 
 }  // namespace
 
@@ -130,11 +130,19 @@ struct brls_ctx {
   brls_grid g{};
   hipStream_t st = nullptr;
   bool own_stream = false;
+  // batched operator launches in two concurrent chains of shot groups:
+  // the second chain's stream, the fork and join events, the stream the
+  // next launch goes to (null: st) and the chain count (1 or 2)
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t lst = nullptr;
+  int chains = 2;
   int device = 0;
   int ndim = 2;
   Geo2D geo{};
   Geo3D geo3{};
   int variant = 0;
+  int bins_variant = 0;  // tile variant the slots' receiver bins are for
   int per_block = 4;      // Born and background launches
   int resident_grid = 0;
   int adj_per_block = 4;  // adjoint launches
@@ -467,9 +475,44 @@ int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
                                               : kTBorn,
                        &t);
   if (rc) return rc;
-  HIPCHECK(c, c->ndim == 3 ? launch_step3d(c->variant, mode, a, c->st)
-                           : launch_step2d(c->variant, mode, a, c->st));
+  hipStream_t ls = c->lst ? c->lst : c->st;
+  HIPCHECK(c, c->ndim == 3 ? launch_step3d(c->variant, mode, a, ls)
+                           : launch_step2d(c->variant, mode, a, ls));
   return timed_end(c, &t);
+}
+
+// The time loop of a batched operator application over the window's shot
+// groups, in one chain of launches or, with two chains, as two independent
+// chains over the first ceil(groups / 2) groups and the rest, the second on
+// its own stream (forked from and joined back to the context's stream):
+// the two run concurrently, so one chain's launches fill the slots the
+// other's leave idle at the end of each launch. body(first, count, group0)
+// enqueues the launches for shots first .. first + count - 1 (window
+// order), groups from group0 on. Not with per-launch timing (the timers
+// bracket launches on the context's stream) or checkpointed backgrounds.
+template <typename F>
+int in_chains(brls_ctx* c, int nsh, int pb, F&& body) {
+  const int ngroups = (nsh + pb - 1) / pb;
+  if (c->chains < 2 || ngroups < 2 || c->timing || c->ckpt_k || !c->st2)
+    return body(0, nsh, 0);
+  const int g0 = (ngroups + 1) / 2;
+  const int s0 = g0 * pb;
+  HIPCHECK(c, hipEventRecord(c->ev_fork, c->st));
+  HIPCHECK(c, hipStreamWaitEvent(c->st2, c->ev_fork, 0));
+  int rc = body(0, s0, 0);
+  if (!rc) {
+    c->lst = c->st2;
+    rc = body(s0, nsh - s0, g0);
+    c->lst = nullptr;
+  }
+  HIPCHECK(c, hipEventRecord(c->ev_join, c->st2));
+  HIPCHECK(c, hipStreamWaitEvent(c->st, c->ev_join, 0));
+  return rc;
+}
+
+std::vector<int> order_part(const brls_ctx* c, int first, int count) {
+  return std::vector<int>(c->order.begin() + first,
+                          c->order.begin() + first + count);
 }
 
 int64_t field_floats(const brls_ctx* c) {
@@ -680,8 +723,12 @@ int enqueue_born(brls_ctx* c, int batched) {
       if ((rc = run(c->tab_dev + k, 1, 1, nt_max_of(c, {c->order[k]}))))
         return rc;
   } else {
-    if ((rc = run(c->tab_dev, nsh, std::min(c->per_block, nsh), ntm)))
-      return rc;
+    const int pb = std::min(c->per_block, nsh);
+    rc = in_chains(c, nsh, pb, [&](int first, int count, int) {
+      return run(c->tab_dev + first, count, pb,
+                 count == nsh ? ntm : nt_max_of(c, order_part(c, first, count)));
+    });
+    if (rc) return rc;
   }
   HIPCHECK(c, launch_born_last(c->tab_dev, nsh, c->g.nrec_max, c->q,
                                two_step(c), c->st));
@@ -777,10 +824,19 @@ int enqueue_adjoint(brls_ctx* c, int batched, double* acc) {
                : adjoint_steps(c, c->tab_dev + k, 1, 1, nt - 1, 1, 0, acc);
       if (rc) return rc;
     }
+  } else if (c->ckpt_k) {
+    if ((rc = adjoint_segments(c, c->tab_dev, nsh, pb, ntm, acc))) return rc;
   } else {
-    rc = c->ckpt_k
-             ? adjoint_segments(c, c->tab_dev, nsh, pb, ntm, acc)
-             : adjoint_steps(c, c->tab_dev, nsh, pb, ntm - 1, 1, 0, acc);
+    rc = in_chains(c, nsh, pb, [&](int first, int count, int group0) {
+      // a chain of shorter shots starts at its own last level, kept at the
+      // parity of the window's so that levels pair into two-step launches
+      // exactly as in one chain (the image sums stay bitwise the same)
+      const int nt = count == nsh ? ntm
+                                  : nt_max_of(c, order_part(c, first, count));
+      const int k_hi = nt - 1 + ((ntm - nt) & (two_step(c) ? 1 : 0));
+      return adjoint_steps(c, c->tab_dev + first, count, pb, k_hi, 1, 0,
+                           acc + (int64_t)group0 * c->mplane);
+    });
     if (rc) return rc;
   }
   HIPCHECK(c, c->ndim == 3
@@ -806,7 +862,8 @@ int run_op(brls_ctx* c, int op) {
   const GraphKey key(op, nsh,
                      adj ? adj_pb(c, nsh) : std::min(c->per_block, nsh),
                      c->variant, nt_max_of(c, c->order),
-                     adj ? c->adj_resident_grid : c->resident_grid, c->exec);
+                     adj ? c->adj_resident_grid : c->resident_grid, c->exec,
+                     c->chains);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     const bool was_timing = c->timing;
@@ -971,6 +1028,17 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
                   "hipGetSymbolAddress of the static scratch: %s",
                   hipGetErrorString(e));
     }
+  }
+  if (hipStreamCreate(&c->st2) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) !=
+          hipSuccess) {
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->st2) (void)hipStreamDestroy(c->st2);
+    if (c->own_stream) (void)hipStreamDestroy(c->st);
+    delete c;
+    return fail(nullptr, BRLS_EDEVICE, "second stream or its events");
   }
   c->ndim = g.ndim;
   const double eta_max = 3.0 * vmax * std::log(1000.0) / (2.0 * g.nb * g.h);
@@ -1159,6 +1227,10 @@ void brls_close(brls_ctx* c) {
     (void)hipEventDestroy(t.b);
   }
   for (void* p : c->allocs) (void)hipFree(p);
+  (void)hipStreamSynchronize(c->st2);
+  (void)hipEventDestroy(c->ev_fork);
+  (void)hipEventDestroy(c->ev_join);
+  (void)hipStreamDestroy(c->st2);
   if (c->own_stream) (void)hipStreamDestroy(c->st);
   delete c;
 }
@@ -1807,6 +1879,20 @@ int brls_apply_adjoint_static(brls_ctx* c, const float* d, float* m_out) {
   return BRLS_OK;
 }
 
+int brls_set_chains(brls_ctx* c, int32_t n) {
+  if (!c) return BRLS_EINVAL;
+  if (n != 1 && n != 2)
+    return fail(c, BRLS_EINVAL, "launch chains: %d (1 or 2)", n);
+  c->chains = n;
+  return BRLS_OK;
+}
+
+int brls_get_chains(const brls_ctx* c, int32_t* n) {
+  if (!c || !n) return BRLS_EINVAL;
+  *n = c->chains;
+  return BRLS_OK;
+}
+
 int brls_set_exec(brls_ctx* c, int32_t mode) {
   if (!c) return BRLS_EINVAL;
   if (mode < BRLS_EXEC_PLAIN || mode > BRLS_EXEC_PERSISTENT)
@@ -1903,17 +1989,24 @@ static int set_tile_impl(brls_ctx* c, int v, int per_block,
   // 3-D kernels advance a fixed number of shots per block together
   if (c->ndim == 3) per_block = adj_per_block = tile_shape3(v).sb;
   HIPCHECK(c, hipStreamSynchronize(c->st));
+  // the geometry follows the variant and (3-D) the z chunk; captured
+  // graphs hold it, the receiver bins follow the variant's tile shape
+  const int old_tiles = c->ndim == 3 ? c->geo3.ntiles : c->geo.ntiles;
+  const int old_tzc = c->geo3.tzc;
   const bool changed = v != c->variant;
   set_variant_geo(c, v);
   c->per_block = per_block;
   c->adj_per_block = adj_per_block;
-  if (changed) {
+  const int new_tiles = c->ndim == 3 ? c->geo3.ntiles : c->geo.ntiles;
+  if (changed || new_tiles != old_tiles || c->geo3.tzc != old_tzc)
     drop_graphs(c);
+  if (v != c->bins_variant) {
     for (auto& sl : c->slots)
       if (sl.used) {
         int rc = build_receiver_tiles(c, sl);
         if (rc) return rc;
       }
+    c->bins_variant = v;
   }
   return BRLS_OK;
 }
@@ -2000,9 +2093,8 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
         }
         if (pb > nsh && pb > 1) break;
         int r;
-        // set_tile_impl rebuilds the geometry (and the z chunk) when the
-        // variant changes; force it for a new z chunk
-        if (c->ndim == 3 && trial == 0) set_variant_geo(c, v);
+        // set_tile_impl sets the geometry for the variant and z chunk and
+        // rebuilds the receiver bins when the tile shape changes
         if ((r = set_tile_impl(c, v, pb, pb))) return r;
         c->resident_grid = c->adj_resident_grid = rg;
         for (int k = 0; k < 2; ++k) {
@@ -2036,14 +2128,12 @@ int brls_autotune(brls_ctx* c, int32_t* best) {
     c->resident_grid = saved_rg;
     c->adj_resident_grid = saved_arg;
     c->zchunk = saved_zc;
-    set_variant_geo(c, c->variant);
     (void)set_tile_impl(c, saved_v, saved_pb, saved_apb);
     return rc;
   }
   c->resident_grid = best_rg;
   c->adj_resident_grid = best_arg;
   c->zchunk = best_zc;
-  set_variant_geo(c, c->variant);
   if ((rc = set_tile_impl(c, best_v, best_pb, best_apb))) return rc;
   if (best) *best = best_v;
   return BRLS_OK;

@@ -1,7 +1,8 @@
 """Execution forms and launch tuning through the C ABI: the persistent
 single-launch operator pair (against batched launches and the oracle, and
-its bounded barrier wait forced to give up), the autotuner (a valid choice,
-the window and image left as they were, results against the oracle after
+its bounded barrier wait forced to give up), two concurrent launch chains
+(against one, bitwise, and the oracle), the autotuner (a valid choice, the
+window and image left as they were, results against the oracle after
 tuning) and the 3-D z chunk."""
 import numpy as np
 import pytest
@@ -177,3 +178,79 @@ def test_autotune_3d_and_z_chunks(P):
     with pytest.raises(P.BrlsError):
         c2.set_zchunk(16)
     c2.close()
+
+
+@pytest.mark.parametrize("tuning", [(24, 1, 5, 1, 5), (18, 1, 0, 1, 1),
+                                    (12, 2, 1, 2, 0)])
+def test_two_chains_bitwise_and_oracle(P, tuning):
+    """The ragged 3-shot window (nt 3 ways, a repeated and deep receivers)
+    with one shot per work item (3 groups: chains of 2 and 1 groups,
+    different lengths): two concurrent launch chains give one chain's
+    results bitwise, in batched and graph modes, and match the oracle."""
+    w = ragged2d()
+    idx = [0, 1, 2]
+    print(f"two chains, launch choice {tuning}", flush=True)
+    ctx = open_ctx(w, q_max=3)
+    ctx.set_tuning(*tuning)
+    assert ctx.get_chains() == 2
+    for i in idx:
+        add_shot(ctx, w, i)
+    m32 = f32(w.m_true)
+    r = np.concatenate([f32(synth.gaussian((w.shots[i].nt, w.shots[i].nrec),
+                                           60 + i)).ravel() for i in idx])
+    out = {}
+    for mode in (P.BRLS_EXEC_BATCHED, P.BRLS_EXEC_GRAPH):
+        ctx.set_exec(mode)
+        for ch in (1, 2):
+            ctx.set_chains(ch)
+            out[(mode, ch)] = (ctx.apply_born(m32), ctx.apply_adjoint(r))
+    d1, g1 = out[(P.BRLS_EXEC_BATCHED, 1)]
+    for d, g in out.values():
+        assert np.array_equal(d, d1) and np.array_equal(g, g1)
+    prob = oracle_problem(w)
+    for g_, w_ in zip(split(w, idx, d1),
+                      prob.born(m32.astype(np.float64), idx)):
+        assert rel(g_, w_) <= OP_TOL
+    assert rel(g1, prob.adjoint([x.astype(np.float64)
+                                 for x in split(w, idx, r)], idx)) <= OP_TOL
+    with pytest.raises(P.BrlsError):
+        ctx.set_chains(3)
+    assert ctx.get_chains() == 2
+    ctx.close()
+
+
+def test_two_chains_window_chain_matches_oracle(P):
+    """The 64 x 64 block-row chain (3 windows of 2 shots, 10 iterations),
+    one shot per work item so that every window's operators run as two
+    concurrent chains, graph mode: the final image against the oracle's."""
+    import oracle
+    w = synth.layers2d_64x64()
+    prob = oracle_problem(w)
+    clean = [prob.born_shot(i, f32(w.m_true).astype(np.float64))
+             for i in range(len(w.shots))]
+    sig = w.noise_rel * np.sqrt(np.mean(np.concatenate(
+        [c.ravel() for c in clean]) ** 2))
+    data = [f32(c + sig * synth.gaussian(c.shape, 4200 + i))
+            for i, c in enumerate(clean)]
+    wins = w.windows()
+    lam = w.lam_rel * oracle.power_norm(prob, wins[0], 10, seed=3)
+    ref = oracle.chain(prob, [d.astype(np.float64) for d in data], wins, lam,
+                       w.niter)
+    ctx = open_ctx(w, lam=lam, q_max=w.Q)
+    ctx.set_tuning(24, 1, 5, 1, 5)
+    held = []
+    for win in wins:
+        for i in list(held):
+            if i not in win:
+                ctx.downdate(i)
+                held.remove(i)
+        for i in win:
+            if i not in held:
+                add_shot(ctx, w, i, data[i])
+                held.append(i)
+        ctx.solve_window(w.niter)
+    img = ctx.image()
+    ctx.close()
+    e = rel(img, ref.m)
+    print(f"two-chain 64x64 chain vs oracle: {e:.2e}")
+    assert e <= IMG_TOL
