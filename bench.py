@@ -429,7 +429,8 @@ def host_window(args, P, w, data, lam, vel, torch):
 def ops_only(P, w, vel, m_true):
     """One 512 MiB device copy (calibrates the memory counters), then one
     batched Born and one adjoint application over the first window (the
-    kernels the timed steps run), for hardware-counter runs."""
+    kernels the timed steps run, one launch chain), for hardware-counter
+    runs."""
     import torch
     src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -443,6 +444,9 @@ def ops_only(P, w, vel, m_true):
         ctx.update(i, s.src, s.rec, s.nt, s.f0, None)
     ctx.set_tuning(*DEFAULT_TUNING)
     ctx.set_exec(P.BRLS_EXEC_BATCHED)
+    # one chain: each launch covers the whole window, as in the per-launch
+    # roofline figures the counters are paired with
+    ctx.set_chains(1)
     ctx.apply_adjoint(ctx.apply_born(m_true))
     torch.cuda.synchronize()
     ctx.close()
