@@ -303,14 +303,15 @@ int brls_background_window(brls_ctx* ctx, float* out);
 int brls_set_exec(brls_ctx* ctx, int32_t mode);
 
 /* Concurrent launch chains of the batched and graph modes (1 or 2; default
- * 2): with 2 and at least two shot groups in the window, each operator
+ * 2 for 2-D contexts with stored Born sources, 1 otherwise): with 2 and at
+ * least two shot groups in the window, each operator
  * application (eqs. 1-2 over the window's shots, eq. 10) runs its time
  * loop as two independent chains of launches, over the first half of the
  * shot groups and the rest, on two streams that run concurrently (the
  * second forked from and joined back to the context's stream, inside a
  * captured graph too). Results are bitwise those of one chain. Not used
- * with per-launch kernel timing, checkpointed backgrounds or persistent
- * launches. Errors: BRLS_EINVAL for other counts. */
+ * with per-launch kernel timing or persistent launches. Errors:
+ * BRLS_EINVAL for other counts. */
 int brls_set_chains(brls_ctx* ctx, int32_t n);
 int brls_get_chains(const brls_ctx* ctx, int32_t* n);
 

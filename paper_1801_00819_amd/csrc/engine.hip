@@ -489,11 +489,11 @@ int step(brls_ctx* c, int mode, int n, const ShotDev* tab, int nshots,
 // other's leave idle at the end of each launch. body(first, count, group0)
 // enqueues the launches for shots first .. first + count - 1 (window
 // order), groups from group0 on. Not with per-launch timing (the timers
-// bracket launches on the context's stream) or checkpointed backgrounds.
+// bracket launches on the context's stream).
 template <typename F>
 int in_chains(brls_ctx* c, int nsh, int pb, F&& body) {
   const int ngroups = (nsh + pb - 1) / pb;
-  if (c->chains < 2 || ngroups < 2 || c->timing || c->ckpt_k || !c->st2)
+  if (c->chains < 2 || ngroups < 2 || c->timing || !c->st2)
     return body(0, nsh, 0);
   const int g0 = (ngroups + 1) / 2;
   const int s0 = g0 * pb;
@@ -759,7 +759,8 @@ int adjoint_segments(brls_ctx* c, const ShotDev* tab, int nsh, int pb,
   for (int seg = nseg_of(c, nt) - 1; seg >= 0; --seg) {
     const int n0 = seg * c->ckpt_k;
     const int n1 = std::min(n0 + c->ckpt_k, nt - 1);
-    HIPCHECK(c, launch_ckpt(tab, nsh, n0, seg, c->fs, 1, c->st));
+    HIPCHECK(c, launch_ckpt(tab, nsh, n0, seg, c->fs, 1,
+                            c->lst ? c->lst : c->st));
     for (int n = n0; n < n1; ++n)
       if ((rc = step(c, kBackground, n, tab, nsh, pb, nullptr, nullptr,
                      nullptr, n0, 1)))
@@ -825,7 +826,16 @@ int enqueue_adjoint(brls_ctx* c, int batched, double* acc) {
       if (rc) return rc;
     }
   } else if (c->ckpt_k) {
-    if ((rc = adjoint_segments(c, c->tab_dev, nsh, pb, ntm, acc))) return rc;
+    // each chain restores its shots' checkpoints, recomputes their
+    // backgrounds segment by segment and runs their adjoint steps (one
+    // step per launch: no level pairing to keep)
+    rc = in_chains(c, nsh, pb, [&](int first, int count, int group0) {
+      const int nt = count == nsh ? ntm
+                                  : nt_max_of(c, order_part(c, first, count));
+      return adjoint_segments(c, c->tab_dev + first, count, pb, nt,
+                              acc + (int64_t)group0 * c->mplane);
+    });
+    if (rc) return rc;
   } else {
     rc = in_chains(c, nsh, pb, [&](int first, int count, int group0) {
       // a chain of shorter shots starts at its own last level, kept at the
@@ -1105,6 +1115,13 @@ int brls_open(const brls_grid* gin, const float* vel, void* stream,
     c->ckpt_k = g.ckpt_interval;
   if (c->ckpt_k) c->nseg_max = (g.nt_max - 1 + c->ckpt_k - 1) / c->ckpt_k;
   if (c->ckpt_k) c->bg64 = 0;  // the background is recomputed in float32
+  // two launch chains by default where they measured faster: 2-D with
+  // stored Born sources (the 512 x 1024 window pair 128 ms against 150 ms).
+  // 3-D launches already hold many work items per shot group (pair
+  // 14.83 s with two chains against 14.13 s), and with checkpoints each
+  // chain's restore-recompute-adjoint segments serialise on its stream
+  // (autograd forward + backward 0.34 s against 0.29 s)
+  c->chains = (g.ndim == 2 && c->ckpt_k == 0) ? 2 : 1;
   if (c->fs >= lim) {  // the storage ring and pitch padding on top
     brls_close(c);
     return fail(nullptr, BRLS_EINVAL,

@@ -254,3 +254,38 @@ def test_two_chains_window_chain_matches_oracle(P):
     e = rel(img, ref.m)
     print(f"two-chain 64x64 chain vs oracle: {e:.2e}")
     assert e <= IMG_TOL
+
+
+@pytest.mark.parametrize("case", ["3d-stored", "3d-ckpt", "2d-ckpt"])
+def test_two_chains_with_checkpoints_bitwise(P, case):
+    """Two launch chains against one, bitwise, where they are not the
+    default: 3-D, and checkpointed backgrounds (each chain restores its
+    shots' checkpoints and recomputes their backgrounds segment by segment;
+    interval 7 in 3-D, 5 in 2-D); graph mode, and the oracle."""
+    w = small3d() if case.startswith("3d") else ragged2d()
+    idx = [0, 1, 2]
+    ckpt = 0 if case == "3d-stored" else (7 if case == "3d-ckpt" else 5)
+    print(f"two chains, {case}", flush=True)
+    ctx = open_ctx(w, q_max=3, ckpt_interval=ckpt)
+    if case == "2d-ckpt":
+        ctx.set_tuning(12, 1, 0, 1, 0)
+    assert ctx.get_chains() == 1  # not the default here
+    for i in idx:
+        add_shot(ctx, w, i)
+    m32 = f32(w.m_true)
+    r = np.concatenate([f32(synth.gaussian((w.shots[i].nt, w.shots[i].nrec),
+                                           80 + i)).ravel() for i in idx])
+    out = {}
+    for ch in (1, 2):
+        ctx.set_chains(ch)
+        out[ch] = (ctx.apply_born(m32), ctx.apply_adjoint(r))
+    ctx.close()
+    assert np.array_equal(out[1][0], out[2][0])
+    assert np.array_equal(out[1][1], out[2][1])
+    prob = oracle_problem(w)
+    for g_, w_ in zip(split(w, idx, out[2][0]),
+                      prob.born(m32.astype(np.float64), idx)):
+        assert rel(g_, w_) <= OP_TOL
+    assert rel(out[2][1], prob.adjoint([x.astype(np.float64)
+                                        for x in split(w, idx, r)],
+                                       idx)) <= OP_TOL
