@@ -12,12 +12,13 @@ both sides use are regenerated here by the same oracle calls and checked
 against the hash stored with the images.
 
 Truncated damped CG is sensitive to rounding at this size: the oracle's own
-20th iterate moves by percents when only its operator operands and results
+20th iterate moves by 5.5 % when only its operator operands and results
 are rounded to float32 (the stored ``images_r32``), from about the 8th
-iteration on. So the chain is checked twice: the 7th iterate of the first
-window, before that sensitivity sets in, to 1e-4; and the 20-iteration
-images and data misfits within twice the distance between the oracle's FP64
-and float32-interface runs (never tighter than 1e-4).
+iteration on. So the chain is checked three ways: the 7th iterate of the
+first window, before that sensitivity sets in, to 1e-4; the first window's
+20th iterate against the oracle's float32-interface run, to 1e-4; and the
+20-iteration images and data misfits of both windows against the FP64 run
+within twice its distance from the float32-interface run.
 """
 import importlib.util
 import json
@@ -158,10 +159,13 @@ def test_full_size_early_iterate_matches_oracle(inputs):
 @pytest.mark.timeout(900)
 def test_full_size_chain_matches_oracle(inputs):
     """The chain's first windows (8 shots sliding by 4, 20 iterations each,
-    the second warm-started from the first's image) against the oracle's
-    stored images and data misfits ||d_w - A_w m||, each within
-    max(1e-4, 2 x the oracle's own FP64 vs float32-interface distance for
-    that window; the first window's where a later one is not stored)."""
+    the second warm-started from the first's image) against the oracle.
+    Window 0 against the oracle's run with float32 operator operands and
+    results (the library's interface precision): image and data misfit
+    ||d_w - A_w m|| to 1e-4. Every window against the FP64 run: image and
+    misfit within max(1e-4, 2 x the distance between the oracle's FP64 and
+    float32-interface runs of window 0), the truncated solve's measured
+    sensitivity to that rounding."""
     mk, w, prob, clean, data, digest = inputs
     g = _golden(digest)
     if "images_r32" not in g.files:
@@ -170,27 +174,35 @@ def test_full_size_chain_matches_oracle(inputs):
     images, im32 = g["images"], g["images_r32"]
     st64 = json.loads(str(g["stats"]))
     st32 = json.loads(str(g["stats_r32"]))
+    img_bound = max(IMG_TOL, 2.0 * rel(im32[0], images[0]))
+    r64, r32 = st64[0]["r_norms"][-1], st32[0]["r_norms"][-1]
+    mis_bound = max(IMG_TOL, 2.0 * abs(r32 - r64) / r64)
     ctx = _window_ctx(w, lam)
     held = []
     fails = []
     for k in range(images.shape[0]):
-        j = min(k, im32.shape[0] - 1)
-        img_bound = max(IMG_TOL, 2.0 * rel(im32[j], images[j]))
-        r64, r32 = st64[j]["r_norms"][-1], st32[j]["r_norms"][-1]
-        mis_bound = max(IMG_TOL, 2.0 * abs(r32 - r64) / r64)
         _load_window(ctx, w, data, mk.WINDOWS[k], held)
         st = ctx.solve_window(mk.NITER)
         assert st["iters"] == mk.NITER
-        e = rel(ctx.image(), images[k])
+        img = ctx.image()
+        e = rel(img, images[k])
         want_r = st64[k]["r_norms"][-1]
         er = abs(st["r_norm"] - want_r) / want_r
-        print(f"window {k}: image vs oracle {e:.2e} (bound {img_bound:.2e}), "
-              f"misfit {st['r_norm']:.6e} vs {want_r:.6e}: {er:.2e} "
-              f"(bound {mis_bound:.2e})", flush=True)
+        print(f"window {k}: vs FP64 oracle image {e:.2e} (bound "
+              f"{img_bound:.2e}), misfit {st['r_norm']:.6e} vs {want_r:.6e}"
+              f" {er:.2e} (bound {mis_bound:.2e})", flush=True)
         if e > img_bound or er > mis_bound:
             fails.append(k)
+        if k < im32.shape[0]:
+            e32 = rel(img, im32[k])
+            w32 = st32[k]["r_norms"][-1]
+            er32 = abs(st["r_norm"] - w32) / w32
+            print(f"window {k}: vs float32-interface oracle image {e32:.2e}, "
+                  f"misfit {er32:.2e}", flush=True)
+            if e32 > IMG_TOL or er32 > IMG_TOL:
+                fails.append(k)
     ctx.close()
-    assert not fails, f"windows {fails} outside the oracle's own spread"
+    assert not fails, f"windows {fails} outside the bounds"
 
 
 STREAM_GOLDEN = os.path.join(HERE, "golden", "stream2d_512x1024_q4_chain2.npz")
